@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark: effective GFLOP/s of exact C = A B mod p on one MI355X.
+
+One step is one call of the library's product entry point on resident
+device inputs: plan, in-kernel word split, word products on the matrix
+cores with in-loop modular reductions, recombination and the single store
+of C (the whole method of Section 3.2).  Effective GFLOP/s is 2 m n k / t
+(the paper's metric, Section 4.1).
+
+Default workload: square m = n = k = 4096 with p the largest prime below
+2^36 and the planner's (u, v); other workloads by --config/--variant.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+INT8_MFMA_PEAK_TOPS = 5000.0
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2601_07508_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        with open(os.path.join(d, fn), "rb") as f:
+            h.update(fn.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, digest):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload)
+    except Exception:
+        return None
+    if not rec or rec.get("source_digest") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(prob, A, B, budget_s=12.0):
+    """The oracle, untuned, on the first rows of the same product."""
+    import numpy as np
+
+    import oracle
+
+    rows = 8
+    while True:  # grow the sample until it takes a sizeable share of the budget
+        t0 = time.perf_counter()
+        oracle.mm_modp(prob.p, np.ascontiguousarray(A[:rows]), B)
+        t = time.perf_counter() - t0
+        if t >= budget_s / 3 or rows >= prob.m:
+            break
+        rows = int(min(prob.m, max(2 * rows, rows * budget_s / max(t, 1e-3))))
+    return {
+        "value": 2.0 * rows * prob.n * prob.k / t / 1e9,
+        "unit": "GFLOP/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"rows 0..{rows - 1} of the {prob.m}x{prob.n}x{prob.k} product "
+                  f"({rows * prob.n} outputs, {t:.1f} s, 128-bit integer dot products)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, help="workload group 1..4")
+    ap.add_argument("--variant", type=int, default=0, help="index inside the workload group")
+    ap.add_argument("--form", type=int, default=0, help="0 auto, 1 FP64 words, 2 INT8 digits")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the product is measured on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mmp_inputs as gen
+    import paper_2601_07508_amd as mmp
+
+    prob = gen.config_problems(args.config)[args.variant]
+    plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, form=args.form)
+    log("workload", prob.tag, "plan", plan)
+
+    A = prob.a()
+    B = prob.b()
+    dA = torch.from_numpy(A.astype(np.float64)).cuda()
+    dB = torch.from_numpy(B.astype(np.float64)).cuda()
+    dC = torch.empty((prob.m, prob.n), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        mmp.mm_modp_async(dA, dB, dC, prob.p, prob.u, prob.v, stream=stream, form=args.form)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms = e0.elapsed_time(e1) / args.steps
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {t_wall:.3f} s)")
+
+    # spot check of the last result against the oracle
+    rows = np.array([0, prob.m - 1, prob.m // 2], dtype=np.int64)
+    cols = np.array([0, prob.n - 1, prob.n // 3], dtype=np.int64)
+    import oracle
+    want = oracle.mm_modp_entries(prob.p, A, B, rows, cols).astype(np.float64)
+    got = dC[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
+    if not np.array_equal(got, want):
+        log("RESULT MISMATCH", got, want)
+        sys.exit(1)
+
+    mnk = float(prob.m) * prob.n * prob.k
+    eff = 2.0 * mnk / (ms * 1e-3) / 1e9
+    uv = plan["u"] * plan["v"]
+    word_tflops = 2.0 * uv * mnk / (ms * 1e-3) / 1e12
+    digest = source_digest()
+    workload = prob.tag
+    roofline = {
+        "bound": "mfma",
+        "achieved": round(word_tflops, 3),
+        "peak": FP64_MFMA_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(word_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+        "traffic": traffic_for(workload, digest),
+        "kernel": "fp64_words_kernel",
+        "algorithmic_flops_per_launch": 2.0 * uv * mnk,
+    }
+    out = {
+        "metric": "effective 2mnk GFLOP/s of C=AB mod p",
+        "value": round(eff, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded uniform integers in [0, p) stored as binary64",
+        "config": {
+            "workload": f"square {prob.m}x{prob.n}x{prob.k}, p = {prob.p} (largest prime below "
+                        f"2^{prob.p.bit_length()}), exact C = AB mod p",
+            "m": prob.m, "n": prob.n, "k": prob.k, "p": prob.p, "bits": prob.p.bit_length(),
+            "u": plan["u"], "v": plan["v"], "lambda": plan["lambda"], "kblock": plan["kblock"],
+            "form": "fp64_words" if plan["form"] == 1 else "int8_digits", "tile": plan["tile"],
+        },
+        "roofline": roofline,
+        "mfma_utilization": round(word_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+        "source_digest": digest,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(prob, A, B)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

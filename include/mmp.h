@@ -1,0 +1,157 @@
+/*
+ * mmp.h -- exact modular matrix multiplication C = A B mod p on MI355X (gfx950).
+ *
+ * The method is the multiword floating-point product of Berthomieu, Graillat,
+ * Lesnoff and Mary, "Multiword matrix multiplication over large finite fields
+ * in floating-point arithmetic":
+ *   - A and B are split into u and v words, A = sum_i alpha^i A_i and
+ *     B = sum_j beta^j B_j with alpha = ceil(p^(1/u)), beta = ceil(p^(1/v))
+ *     (Section 3.1, Alg. 4);
+ *   - the uv word products A_i B_j are accumulated in binary64, reduced mod p
+ *     with the fma-based reduction (Section 2.1, Alg. 1) after every k-block
+ *     whose length respects the block-size bound (Section 2.2, Prop.
+ *     blockProduct; Section 3.2, Prop. UVMW, eq. cAcB);
+ *   - the products are recombined mod p (Section 3.2, eq. for AB as a sum
+ *     over (i, j) of alpha^i beta^j A_i B_j), here by a Horner scheme with the
+ *     modular product reduction (Section 2.1, Alg. 2).
+ *
+ * Conventions for every entry point below:
+ *   - Matrices are row-major.  A is m x k with leading dimension lda >= k,
+ *     B is k x n with ldb >= n, C is m x n with ldc >= n.
+ *   - FP64 matrices hold integers in [0, p) (the representation of F_p used
+ *     throughout the paper).  Results are bit-exact: C[i][j] is the unique
+ *     integer in [0, p) congruent to sum_l A[i][l] B[l][j], stored as +0.0 ..
+ *     p-1 in binary64.
+ *   - Matrix pointers are DEVICE pointers (memory of the current HIP device).
+ *     The caller owns A, B and C and keeps them alive until the call has
+ *     completed in stream order.  C must not overlap A or B.
+ *   - A stream argument is a hipStream_t passed as void*; NULL is the null
+ *     stream.  Calls with a stream are asynchronous unless stated otherwise.
+ *   - The modulus must satisfy 5 <= p < 2^52 (the paper assumes p >= 5 and
+ *     Alg. 1 needs p < 2^(t-1) with t = 53).  Primality is not required: the
+ *     recombination used here needs no modular inverse.
+ *   - m, n or k may be 0; with k = 0 the result C is all zeros.
+ *   - Errors are returned as negative mmp_status values; no entry point
+ *     aborts or lets a C++ exception escape.
+ */
+#ifndef MMP_H
+#define MMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MMP_OK = 0,
+  MMP_EINVAL = -1,      /* null pointer, negative size, bad leading dimension,
+                           p outside [5, 2^52), unsupported (u, v) or option */
+  MMP_EBOUND = -2,      /* the requested (u, v) admits no block size >= 1 for
+                           this p, or a forced k-block exceeds the bound */
+  MMP_ERANGE = -3,      /* entry validation found an entry outside [0, p) or
+                           a non-integral entry */
+  MMP_ENOMEM = -4,      /* device or host allocation failed */
+  MMP_EHIP = -5,        /* HIP runtime error; see mmp_last_hip_error() */
+  MMP_EBUSY = -6,       /* server admission rejected (non-blocking submit) */
+  MMP_ENOTFOUND = -7,   /* unknown server ticket or operand handle */
+  MMP_ETIMEOUT = -8     /* mmp_wait timed out */
+} mmp_status;
+
+/* Word forms. */
+enum {
+  MMP_FORM_AUTO = 0,        /* planner picks the faster form for (p, shape) */
+  MMP_FORM_FP64_WORDS = 1,  /* the paper's binary64 words on FP64 MFMA */
+  MMP_FORM_INT8_WORDS = 2   /* signed 8-bit digits on INT8 MFMA, int32
+                               accumulation, binary64 reduction/recombination */
+};
+
+/* Options; a NULL mmp_opts* means all fields zero. */
+typedef struct {
+  int form;               /* MMP_FORM_* */
+  int64_t force_kblock;   /* 0: planner's k-block; else the number of k-terms
+                             accumulated between reductions (<= the bound) */
+  int validate_entries;   /* 1: check every entry of A and B lies in [0, p)
+                             and is integral before computing (MMP_ERANGE) */
+  int tile;               /* 0: planner's tile; else a tile id from mmp_plan_t */
+  int strict_fmod;        /* 1: every in-loop reduction is the full Alg. 1;
+                             0: the planner may use the correction-free form
+                             where its range check allows (see mmp_plan_t) */
+  int reserved[7];        /* must be zero */
+} mmp_opts;
+
+/* What the planner decided for one product (mmp_plan fills it). */
+typedef struct {
+  uint64_t p;
+  int u, v;               /* words of A and of B */
+  int form;               /* MMP_FORM_FP64_WORDS or MMP_FORM_INT8_WORDS */
+  uint64_t alpha, beta;   /* ceil(p^(1/u)), ceil(p^(1/v)) (FP64 form) */
+  int64_t lambda;         /* the paper's block size: eq. lambda-sw for (1,1),
+                             eq. cAcB otherwise (FP64 form) */
+  int64_t kblock;         /* k-terms accumulated between reductions (<= lambda) */
+  int slots;              /* MFMA k-slots that hold one k-block (>= kblock;
+                             the excess slots hold zeros) */
+  int lazy;               /* 1: in-loop reductions omit Alg. 1's corrections
+                             (result in [-p, 2p)); the final one is complete */
+  int tile;               /* kernel tile id */
+  int bm, bn, bk;         /* workgroup tile (rows, cols, k-slots per stage) */
+  int digits_a, digits_b; /* INT8 form: signed base-256 digits per operand */
+  int64_t kblock_int8;    /* INT8 form: k-terms per int32 accumulation block */
+  double q;               /* fl(1/p) */
+  double est_seconds;     /* planner's cost-model estimate (0 if unknown) */
+  size_t workspace_bytes; /* device workspace the call needs */
+} mmp_plan_t;
+
+/* One product of a batch. */
+typedef struct {
+  uint64_t p;
+  int u, v;               /* 0, 0: planner's choice */
+  int64_t m, n, k;
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  double *C;
+  int64_t ldc;
+} mmp_job;
+
+/* ---------------------------------------------------------------- core */
+
+/* C = A B mod p, synchronous (returns after C is written), null stream,
+ * contiguous matrices (lda = k, ldb = n, ldc = n).  u = v = 0 lets the
+ * planner pick the words; otherwise 1 <= u, v <= 4 with u v <= 8.
+ * Defined by Section 1 eq. goal; computed by the method of Section 3.2. */
+int mm_modp(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k,
+            const double *A, const double *B, double *C);
+
+/* Same product with options, strides and a stream; asynchronous. */
+int mm_modp_async(const mmp_opts *opts, uint64_t p, int u, int v, int64_t m,
+                  int64_t n, int64_t k, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, double *C, int64_t ldc,
+                  void *stream);
+
+/* ---------------------------------------------------------------- planning */
+
+/* Fills *out with the plan mm_modp_async would use (host-only; touches no
+ * device).  Word counts and block size follow Section 3.3 (Table
+ * tab.summary and the bitsize ranges after it) and Prop. UVMW. */
+int mmp_plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k,
+             const mmp_opts *opts, mmp_plan_t *out);
+
+/* Device bytes a job occupies: its operands and result (8 (mk + kn + mn))
+ * plus its word copies (FP64 words: 8 (u mk + v kn); INT8 digits:
+ * da mk + db kn), per the storage cost of Section 3.3. */
+size_t mmp_footprint(const mmp_job *job, const mmp_plan_t *plan);
+
+/* Static description of a status code (never NULL). */
+const char *mmp_strerror(int status);
+
+/* The hipError_t of the last MMP_EHIP on this thread (0 if none). */
+int mmp_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMP_H */

@@ -1,0 +1,35 @@
+// One (u, v) word pair of the fused FP64-word kernel, selected at build time
+// by MMP_U and MMP_V, so that the pairs compile in parallel.
+#include "fp64_words_kernel.h"
+
+#if !defined(MMP_U) || !defined(MMP_V)
+#error "build with -DMMP_U=<u> -DMMP_V=<v>"
+#endif
+
+#define MMP_CAT2(a, b, c) a##b##_##c
+#define MMP_CAT(a, b, c) MMP_CAT2(a, b, c)
+
+namespace mmp {
+
+int MMP_CAT(launch_fp64_words_, MMP_U, MMP_V)(int tile_id, const Fp64Args& a, void* stream) {
+  using namespace fp64w;
+  static_assert(MMP_U * MMP_V <= kMaxWordProducts, "unsupported word pair");
+  constexpr int UV = MMP_U * MMP_V;
+  hipStream_t s = (hipStream_t)stream;
+  (void)UV;
+  // k-steps per in-loop reduction: S / 4 for S in {4, 8}, else 4 (whole stages)
+  const int fe = a.S == 4 ? 1 : a.S == 8 ? 2 : 4;
+#define MMP_SHAPE(ID_)                                                  \
+  if (tile_id == ID_) {                                                 \
+    if (fe == 1) return launch_shape<MMP_U, MMP_V, ID_, 1>(a, s);       \
+    if (fe == 2) return launch_shape<MMP_U, MMP_V, ID_, 2>(a, s);       \
+    return launch_shape<MMP_U, MMP_V, ID_, 4>(a, s);                    \
+  }
+  MMP_SHAPE(1)
+  MMP_SHAPE(2)
+  MMP_SHAPE(3)
+#undef MMP_SHAPE
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace mmp

@@ -1,0 +1,204 @@
+// Planner: word counts, scaling parameters, block size and tile for one
+// product.  Pure host integer arithmetic; touches no device.
+//
+// Paper passages implemented here:
+//   alpha = ceil(p^(1/u))                       Section 3.1, Alg. 4
+//   block size, (1,1): eq. lambda-sw            Section 2.2
+//   block size, (u,v): lambda alpha beta + p - 1 <= 2^t, eq. cAcB, Prop. UVMW
+//   (u,v) choice by bitsize and cost            Section 3.3, Table tab.summary
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "mmp_internal.h"
+
+namespace mmp {
+
+typedef unsigned __int128 u128;
+
+uint64_t iroot_ceil(uint64_t p, int u) {
+  if (u <= 1) return p;
+  // start from the floating-point root, then fix up with exact powers
+  uint64_t a = (uint64_t)std::llround(std::pow((double)p, 1.0 / u));
+  if (a < 1) a = 1;
+  auto pow_ge = [&](uint64_t base) {  // base^u >= p, exact
+    u128 r = 1;
+    for (int i = 0; i < u; i++) {
+      r *= base;
+      if (r >= p) return true;
+    }
+    return r >= p;
+  };
+  while (!pow_ge(a)) a++;
+  while (a > 1 && pow_ge(a - 1)) a--;
+  return a;
+}
+
+bool supported_words(int u, int v) {
+  return u >= 1 && v >= 1 && u <= kMaxWords && v <= kMaxWords && u * v <= kMaxWordProducts;
+}
+
+// Largest word product the paper's bound charges per k-term.
+static u128 word_product_bound(uint64_t p, int u, int v) {
+  if (u == 1 && v == 1) return (u128)(p - 1) * (u128)(p - 1);  // eq. lambda-sw
+  return (u128)iroot_ceil(p, u) * (u128)iroot_ceil(p, v);     // eq. cAcB
+}
+
+int64_t paper_lambda(uint64_t p, int u, int v) {
+  if (p < 5 || p >= kPMax) return 0;
+  u128 w = word_product_bound(p, u, v);
+  u128 room = (u128)kTwoT - p + 1;  // lambda w + p - 1 <= 2^t
+  u128 lam = room / w;
+  if (lam > (u128)INT64_MAX) lam = INT64_MAX;
+  return (int64_t)lam;
+}
+
+bool lazy_block_ok(uint64_t p, int u, int v, int64_t L) {
+  // A block starts from a value in [-p, 2p - 1] and adds L non-negative
+  // terms, each at most w: every partial sum stays in [-p, 2^t] if
+  // L w + 2p - 1 <= 2^t.
+  u128 w = word_product_bound(p, u, v);
+  return (u128)L * w + 2 * (u128)p - 1 <= (u128)kTwoT;
+}
+
+namespace {
+
+// Relative cost per real k-term of one 16x16 output tile, in SIMD cycles,
+// measured shape of the gfx950 pipes: an FP64 16x16x4 MFMA issues every 64
+// cycles and FP64 VALU instructions (4 cycles each) do not overlap with it.
+// An in-loop reduction of a 16x16 tile is 4 values per lane: 3 VALU ops
+// each when correction-free, about 11 with Alg. 1's two corrections.
+double block_cost(int S, int64_t L, bool lazy) {
+  const double mfma = 64.0 * (S / 4);
+  const double red = lazy ? 4 * 3 * 4.0 : 4 * 11 * 4.0;
+  return (mfma + red) / (double)L;
+}
+
+struct KBlock {
+  int64_t L;
+  int S;
+  bool lazy;
+  double cost;
+};
+
+KBlock choose_kblock(uint64_t p, int u, int v, int64_t lambda, int64_t k, bool strict) {
+  KBlock best{0, 0, false, 1e300};
+  auto consider = [&](int S, int64_t L) {
+    if (L < 1 || L > lambda) return;
+    bool lazy = !strict && lazy_block_ok(p, u, v, L);
+    double c = block_cost(S, L, lazy);
+    // a block longer than k never reduces in the loop: cost of the MFMAs only
+    if (L >= k && k > 0) c = 64.0 * (S / 4) / (double)L;
+    if (c < best.cost - 1e-12) best = {L, S, lazy, c};
+  };
+  for (int S : {4, 8, 16}) consider(S, lambda < S ? lambda : S);
+  // multi-stage blocks (no zero slots): L = S = 16 j
+  int64_t jmax = lambda / kBK;
+  if (jmax >= 2) {
+    int64_t cap = (int64_t)1 << 26;  // beyond this the in-loop cost is nil
+    int64_t j = jmax * kBK > cap ? cap / kBK : jmax;
+    consider((int)std::min<int64_t>(j * kBK, cap), j * kBK);
+  }
+  return best;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int pick_tile(int uv, int64_t m, int64_t n) {
+  for (int id = 1; id <= 3; id++) {
+    Fp64Tile t = fp64_tile(id, uv);
+    int64_t nb = cdiv(m, fp64_bm(t)) * cdiv(n, fp64_bn(t));
+    if (nb >= 512) return id;
+  }
+  return 3;
+}
+
+}  // namespace
+
+int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
+         mmp_plan_t* out) {
+  if (!out) return MMP_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  mmp_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  for (int r : o.reserved)
+    if (r != 0) return MMP_EINVAL;
+  if (p < 5 || p >= kPMax) return MMP_EINVAL;
+  if (m < 0 || n < 0 || k < 0) return MMP_EINVAL;
+  if ((u == 0) != (v == 0)) return MMP_EINVAL;
+  if (u != 0 && !supported_words(u, v)) return MMP_EINVAL;
+  if (o.form != MMP_FORM_AUTO && o.form != MMP_FORM_FP64_WORDS) return MMP_EINVAL;
+  if (o.force_kblock < 0 || o.tile < 0 || o.tile > 3) return MMP_EINVAL;
+
+  const bool strict = o.strict_fmod != 0;
+
+  // Candidate word pairs.  With u = v = 0 the planner takes the cheapest by
+  // the cost model (uv word products, each at its own block cost), which
+  // reproduces the bitsize ranges after Table tab.summary; ties go to the
+  // orientation that puts extra words on the operand with the smaller outer
+  // dimension (the concatenation rule of Section 3.2).
+  static const int cand[][2] = {{1, 1}, {1, 2}, {2, 1}, {1, 3}, {3, 1}, {2, 2},
+                                {1, 4}, {4, 1}, {2, 3}, {3, 2}, {2, 4}, {4, 2}};
+  int bu = u, bv = v;
+  KBlock bk{};
+  if (u == 0) {
+    double best = 1e300;
+    for (auto& c : cand) {
+      int cu = c[0], cv = c[1];
+      if (n < m && cu > cv) continue;  // words on B when B is the narrower side
+      if (n > m && cv > cu) continue;
+      int64_t lam = paper_lambda(p, cu, cv);
+      if (lam < 1) continue;
+      KBlock kb = choose_kblock(p, cu, cv, lam, k, strict);
+      double cost = kb.cost * cu * cv;
+      if (cost < best * (1 - 1e-9)) {
+        best = cost;
+        bu = cu;
+        bv = cv;
+        bk = kb;
+      }
+    }
+    if (best >= 1e299) return MMP_EBOUND;
+  }
+  const int64_t lambda = paper_lambda(p, bu, bv);
+  if (lambda < 1) return MMP_EBOUND;
+  if (o.force_kblock > 0) {
+    int64_t L = o.force_kblock;
+    if (L > lambda) return MMP_EBOUND;
+    int S;
+    if (L <= 4) S = 4;
+    else if (L <= 8) S = 8;
+    else if (L <= kBK) S = kBK;
+    else if (L % kBK == 0) S = (int)std::min<int64_t>(L, (int64_t)1 << 26);
+    else return MMP_EINVAL;  // longer blocks must be whole LDS stages
+    if (L > ((int64_t)1 << 26)) return MMP_EINVAL;
+    bk = {L, S, !strict && lazy_block_ok(p, bu, bv, L), block_cost(S, L, false)};
+  } else if (u != 0) {
+    bk = choose_kblock(p, bu, bv, lambda, k, strict);
+  }
+
+  out->p = p;
+  out->u = bu;
+  out->v = bv;
+  out->form = MMP_FORM_FP64_WORDS;
+  out->alpha = iroot_ceil(p, bu);
+  out->beta = iroot_ceil(p, bv);
+  out->lambda = lambda;
+  out->kblock = bk.L;
+  out->slots = bk.S;
+  out->lazy = bk.lazy ? 1 : 0;
+  out->tile = o.tile ? o.tile : pick_tile(bu * bv, m, n);
+  Fp64Tile t = fp64_tile(out->tile, bu * bv);
+  out->bm = fp64_bm(t);
+  out->bn = fp64_bn(t);
+  out->bk = kBK;
+  out->q = 1.0 / (double)p;
+  // cycles per 16x16 tile per k-term, over 1024 SIMDs at 2.4 GHz
+  double tiles = (double)cdiv(m, 16) * (double)cdiv(n, 16);
+  out->est_seconds = tiles * (double)k * bk.cost * bu * bv / (1024.0 * 2.4e9);
+  out->workspace_bytes = 0;
+  return MMP_OK;
+}
+
+}  // namespace mmp

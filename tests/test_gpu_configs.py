@@ -1,0 +1,102 @@
+"""The benchmark workloads at full size, checked on sampled outputs.
+
+Each product runs through the same entry point and plan as the benchmark.
+The oracle recomputes whole sampled rows and columns plus random entries
+exactly; every output is also checked to be an integer in [0, p).
+The 512^3 workload is small enough to compare in full.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import mmp_inputs as gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mmp = pytest.importorskip("paper_2601_07508_amd")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _compute(prob, **opts):
+    A = prob.a()
+    B = prob.b()
+    dA = torch.from_numpy(A.astype(np.float64)).cuda()
+    dB = torch.from_numpy(B.astype(np.float64)).cuda()
+    C = torch.full((prob.m, prob.n), -1.0, dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(dA, dB, C, prob.p, prob.u, prob.v, **opts)
+    torch.cuda.synchronize()
+    del dA, dB
+    return A, B, C
+
+
+def _check_sampled(prob, A, B, C, nrows=2, ncols=2, nrand=512):
+    p = prob.p
+    assert bool(torch.all((C >= 0) & (C < p) & (C == torch.floor(C))))
+    assert not bool(torch.any(torch.signbit(C)))
+    rng = gen.uniform_mod(prob.seed, 77, nrows + ncols + 2 * nrand, 1 << 62)
+    rows = [int(x) % prob.m for x in rng[:nrows]] + [prob.m - 1]
+    cols = [int(x) % prob.n for x in rng[nrows:nrows + ncols]] + [prob.n - 1]
+    rr, cc = [], []
+    for r in rows:
+        rr += [r] * prob.n
+        cc += list(range(prob.n))
+    for c in cols:
+        rr += list(range(prob.m))
+        cc += [c] * prob.m
+    rand = rng[nrows + ncols:]
+    rr += [int(x) % prob.m for x in rand[:nrand]]
+    cc += [int(x) % prob.n for x in rand[nrand:]]
+    rr = np.array(rr, dtype=np.int64)
+    cc = np.array(cc, dtype=np.int64)
+    want = oracle.mm_modp_entries(p, A, B, rr, cc).astype(np.float64)
+    got = C[torch.from_numpy(rr).cuda(), torch.from_numpy(cc).cuda()].cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} sampled mismatches, first ({rr[bad[0]]},{cc[bad[0]]})"
+
+
+def test_square_512_b25_full():
+    (prob,) = gen.config_problems(1)
+    say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
+    A, B, C = _compute(prob)
+    want = oracle.mm_modp(prob.p, A, B).astype(np.float64)
+    assert np.array_equal(C.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_square_4096(idx):
+    prob = gen.config_problems(2)[idx]
+    say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
+    A, B, C = _compute(prob)
+    _check_sampled(prob, A, B, C)
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_square_8192_b50_22(idx):
+    prob = gen.config_problems(3)[idx]
+    say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
+    A, B, C = _compute(prob)
+    if prob.fill == "pmax":
+        # (p-1)^2 = 1 mod p: every entry is k mod p
+        assert bool(torch.all(C == float(prob.k % prob.p)))
+    _check_sampled(prob, A, B, C, nrows=1, ncols=1, nrand=256)
+
+
+@pytest.mark.parametrize("idx", list(range(8)))
+def test_sweep_shapes(idx):
+    prob = gen.config_problems(4)[idx]
+    say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
+    A, B, C = _compute(prob)
+    _check_sampled(prob, A, B, C, nrows=1, ncols=1, nrand=512)

@@ -1,0 +1,190 @@
+"""GPU parity of the fused FP64-word path against the exact oracle.
+
+Tolerance: none.  C = A B mod p has exactly one correct value per entry
+(Section 1, eq. goal; Section 3.2, Prop. UVMW), so every entry must equal
+the oracle's bit for bit, +0.0 included.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import mmp_inputs as gen
+import oracle
+from oracle import paper_algorithms as pa
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mmp = pytest.importorskip("paper_2601_07508_amd")
+
+SUPPORTED = [(1, 1), (1, 2), (2, 1), (1, 3), (3, 1), (2, 2), (1, 4), (4, 1), (2, 3), (3, 2), (2, 4), (4, 2)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def run(p, A, B, u=0, v=0, **opts):
+    m, n = A.shape[0], B.shape[1]
+    C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(dev(A), dev(B), C, p, u, v, **opts)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+def assert_exact(got, want):
+    assert got.dtype == np.float64
+    w = want.astype(np.float64)
+    bad = np.nonzero(got != w)
+    assert bad[0].size == 0, f"{bad[0].size} mismatches, first at {bad[0][0]},{bad[1][0]}: {got[bad][0]} vs {w[bad][0]}"
+    assert not np.any(np.signbit(got)), "negative zero in output"
+
+
+PRIMES = [5, 7, 1048573, 8388593, 33554393, 67108859, 2147483647, 34359738337, 68719476731,
+          1099511627689, 1125899906842597, 4503599627370449]
+SHAPES = [(1, 1, 1), (17, 33, 29), (64, 64, 64), (100, 70, 300), (130, 129, 67)]
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_parity_all_word_pairs(p):
+    for (u, v) in SUPPORTED:
+        if pa.block_size(p, u, v) < 1:
+            continue
+        for (m, n, k) in SHAPES:
+            say("parity", p, u, v, m, n, k)
+            A = gen.random_matrix(p + m, 1, m, k, p)
+            B = gen.random_matrix(p + n, 2, k, n, p)
+            assert_exact(run(p, A, B, u, v), oracle.mm_modp(p, A, B))
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_parity_auto_plan(p):
+    for (m, n, k) in [(65, 200, 131), (256, 256, 1000)]:
+        say("auto", p, m, n, k, mmp.plan(p, m, n, k))
+        A = gen.random_matrix(3, 1, m, k, p)
+        B = gen.random_matrix(3, 2, k, n, p)
+        assert_exact(run(p, A, B), oracle.mm_modp(p, A, B))
+
+
+# each (u, v) at its bitsize limit (Table tab.summary), all entries p - 1
+LIMITS = [((1, 1), 26), ((1, 2), 35), ((2, 1), 35), ((1, 3), 39), ((1, 4), 42), ((2, 2), 52), ((2, 3), 52),
+          ((3, 2), 52), ((2, 4), 52)]
+
+
+@pytest.mark.parametrize("uv,bits", LIMITS)
+def test_worst_case_at_bitsize_limit(uv, bits):
+    u, v = uv
+    p = gen.prev_prime(1 << bits)
+    assert pa.block_size(p, u, v) >= 1
+    a_ = pa.iroot_ceil(p, u)
+    x_low = ((p - 1) // a_) * a_ - 1 if u > 1 else p - 1  # low word alpha - 1
+    for strict in (False, True):
+        for fill in (p - 1, x_low):
+            m, n, k = 40, 36, 301
+            A = np.full((m, k), fill, dtype=np.uint64)
+            B = np.full((k, n), p - 1, dtype=np.uint64)
+            say("worst", u, v, p, fill, strict)
+            assert_exact(run(p, A, B, u, v, strict_fmod=strict), oracle.mm_modp(p, A, B))
+
+
+@pytest.mark.parametrize("p,u,v", [(33554393, 1, 1), (1125899906842597, 2, 2), (68719476731, 1, 3),
+                                   (4503599627370449, 2, 3)])
+def test_every_forced_kblock(p, u, v):
+    lam = pa.block_size(p, u, v)
+    Ls = list(range(1, min(lam, 16) + 1)) + ([32, 48] if lam >= 48 else [])
+    m, n, k = 33, 47, 203
+    A = gen.random_matrix(11, 1, m, k, p)
+    B = np.full((k, n), p - 1, dtype=np.uint64)
+    want = oracle.mm_modp(p, A, B)
+    for L in Ls:
+        for strict in (False, True):
+            say("kblock", p, u, v, L, strict)
+            assert_exact(run(p, A, B, u, v, force_kblock=L, strict_fmod=strict), want)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_every_tile_shape(tile):
+    for p, (u, v) in [(33554393, (1, 1)), (34359738337, (1, 2)), (68719476731, (1, 3)),
+                      (1125899906842597, (2, 2)), (1125899906842597, (2, 3)), (2147483647, (2, 4)),
+                      (2147483647, (4, 2)), (2147483647, (3, 1)), (2147483647, (4, 1))]:
+        m, n, k = 150, 137, 77
+        say("tile", tile, p, u, v)
+        A = gen.random_matrix(5, 1, m, k, p)
+        B = gen.random_matrix(5, 2, k, n, p)
+        assert_exact(run(p, A, B, u, v, tile=tile), oracle.mm_modp(p, A, B))
+
+
+def test_zero_k_and_empty():
+    p = 33554393
+    C = torch.full((5, 7), 3.0, dtype=torch.float64, device="cuda")
+    A = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
+    B = torch.zeros((0, 7), dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(A, B, C, p)
+    torch.cuda.synchronize()
+    assert torch.all(C == 0) and not torch.any(torch.signbit(C))
+    E = torch.zeros((0, 7), dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                      torch.zeros((3, 7), dtype=torch.float64, device="cuda"), E, p)
+
+
+def test_strided_operands_and_stream():
+    p = 1099511627689
+    m, n, k = 70, 50, 90
+    A = gen.random_matrix(8, 1, m, k, p)
+    B = gen.random_matrix(8, 2, k, n, p)
+    Ab = torch.zeros((m, k + 13), dtype=torch.float64, device="cuda")
+    Bb = torch.zeros((k, n + 5), dtype=torch.float64, device="cuda")
+    Cb = torch.full((m, n + 9), 7.0, dtype=torch.float64, device="cuda")
+    Ab[:, :k] = dev(A)
+    Bb[:, :n] = dev(B)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    mmp.mm_modp_async(Ab[:, :k], Bb[:, :n], Cb[:, :n], p, 2, 2, stream=s)
+    s.synchronize()
+    out = Cb.cpu().numpy()
+    assert_exact(out[:, :n], oracle.mm_modp(p, A, B))
+    assert np.all(out[:, n:] == 7.0)  # padding columns untouched
+
+
+def test_sync_entry_point():
+    p = 8388593
+    A = gen.random_matrix(9, 1, 31, 45, p)
+    B = gen.random_matrix(9, 2, 45, 29, p)
+    C = torch.empty((31, 29), dtype=torch.float64, device="cuda")
+    mmp.mm_modp_sync(dev(A), dev(B), C, p)
+    assert_exact(C.cpu().numpy(), oracle.mm_modp(p, A, B))
+
+
+def test_validate_entries():
+    p = 33554393
+    A = gen.random_matrix(4, 1, 20, 20, p).astype(np.float64)
+    B = gen.random_matrix(4, 2, 20, 20, p).astype(np.float64)
+    C = torch.empty((20, 20), dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(dev(A), dev(B), C, p, validate_entries=True)  # clean inputs pass
+    for bad in (float(p), -1.0, 0.5, float("nan")):
+        A2 = A.copy()
+        A2[3, 7] = bad
+        with pytest.raises(mmp.MmpError) as e:
+            mmp.mm_modp_async(dev(A2), dev(B), C, p, validate_entries=True)
+        assert e.value.status == -3
+
+
+def test_composite_modulus():
+    # the Horner recombination needs no modular inverse: composite p works
+    for p in (2**20, 3**20, 10**12 + 1, 2**51 - 1):
+        A = gen.random_matrix(p % 97, 1, 40, 90, p)
+        B = gen.random_matrix(p % 89, 2, 90, 33, p)
+        say("composite", p)
+        assert_exact(run(p, A, B), oracle.mm_modp(p, A, B))

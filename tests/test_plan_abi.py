@@ -1,0 +1,248 @@
+"""Host-side checks of the C library: exported symbols, planner, argument errors.
+
+None of these calls touch a GPU (the planner is host integer arithmetic and
+argument errors are returned before any device work).
+"""
+
+import ctypes
+import json
+import math
+import os
+import re
+
+import pytest
+
+import mmp_inputs as gen
+from oracle import paper_algorithms as pa
+from tests.conftest import PRIMES
+
+mmp = pytest.importorskip("paper_2601_07508_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+TWO_T = 1 << 53
+
+
+def header_functions():
+    """Every function declared in include/*.h."""
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*\b([a-z_][a-z0-9_]*)\s*\(",
+                                src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert "mm_modp" in names and "mmp_plan" in names
+    lib = mmp.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_covers_all_codes():
+    for code in range(0, -9, -1):
+        s = mmp.strerror(code)
+        assert s and s != "unknown status"
+    assert mmp.strerror(12345) == "unknown status"
+
+
+SUPPORTED = [(1, 1), (1, 2), (2, 1), (1, 3), (3, 1), (2, 2), (1, 4), (4, 1), (2, 3), (3, 2), (2, 4), (4, 2)]
+
+
+def test_plan_matches_oracle_lambda_table():
+    rows = json.load(open(os.path.join(GOLDEN, "lambda_table.json")))["rows"]
+    checked = 0
+    for r in rows:
+        p, u, v = r["p"], r["u"], r["v"]
+        if (u, v) not in SUPPORTED:
+            continue
+        if r["lambda"] < 1:
+            with pytest.raises(mmp.MmpError) as e:
+                mmp.plan(p, 64, 64, 64, u, v)
+            assert e.value.status == -2
+            continue
+        pl = mmp.plan(p, 64, 64, 64, u, v)
+        assert (pl["alpha"], pl["beta"], pl["lambda"]) == (r["alpha"], r["beta"], r["lambda"]), r
+        checked += 1
+    assert checked > 50
+
+
+def _tight_lazy_ok(p, u, v, L):
+    """Independent re-derivation: a block starting in [-p, 2p) with L products
+    of words below alpha and beta stays within 2^t."""
+    a, b = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+    w = (p - 1) ** 2 if (u, v) == (1, 1) else (a - 1) * (b - 1)
+    return L * w + 2 * p - 1 <= TWO_T
+
+
+@pytest.mark.parametrize("p", PRIMES[2:])
+@pytest.mark.parametrize("uv", SUPPORTED)
+@pytest.mark.parametrize("k", [1, 7, 100, 4096, 131072])
+def test_plan_invariants(p, uv, k):
+    u, v = uv
+    lam = pa.block_size(p, u, v)
+    if lam < 1:
+        return
+    for strict in (False, True):
+        pl = mmp.plan(p, 256, 256, k, u, v, strict_fmod=strict)
+        L, S = pl["kblock"], pl["slots"]
+        assert 1 <= L <= lam
+        assert S >= L and (S in (4, 8, 16) or (S % 16 == 0 and S == L))
+        if pl["lazy"]:
+            assert not strict and _tight_lazy_ok(p, u, v, L)
+        assert pl["q"] == 1.0 / p
+        assert pl["bk"] == 16 and pl["tile"] in (1, 2, 3)
+
+
+def test_auto_choice_follows_bitsize():
+    # Section 3.3: (1,1) for small primes; multiword beyond 26 bits; at 52
+    # bits the (2,3)-product (the (2,2) block size is 1 there).
+    assert (mmp.plan(1048573, 1024, 1024, 1024)["u"], mmp.plan(1048573, 1024, 1024, 1024)["v"]) == (1, 1)
+    for b in range(27, 53):
+        pl = mmp.plan(gen.prev_prime(1 << b), 2048, 2048, 2048)
+        assert pa.block_size(pl["p"], pl["u"], pl["v"]) >= 1
+        assert pl["u"] * pl["v"] >= 2
+    pl = mmp.plan(4503599627370449, 2048, 2048, 2048)
+    assert pl["u"] * pl["v"] == 6
+
+
+def test_auto_orientation_skinny():
+    p = 68719476731  # 36 bits: needs a (1, v) or (v, 1) split
+    pl = mmp.plan(p, 16384, 32, 4096)  # n < m: extra words on B
+    assert pl["v"] >= pl["u"]
+    pl = mmp.plan(p, 32, 16384, 4096)
+    assert pl["u"] >= pl["v"]
+
+
+@pytest.mark.parametrize("args,status", [
+    ((4, 1, 1), -1), ((1 << 52, 2, 2), -1), ((33554393, 5, 1), -1), ((33554393, 3, 3), -1),
+    ((33554393, 1, 0), -1), ((2147483647, 1, 1), -2), ((4503599627370449, 1, 2), -2),
+])
+def test_plan_errors(args, status):
+    p, u, v = args
+    with pytest.raises(mmp.MmpError) as e:
+        mmp.plan(p, 8, 8, 8, u, v)
+    assert e.value.status == status
+
+
+def test_forced_kblock():
+    p = 1125899906842597  # (2,2): lambda = 7
+    for L in range(1, 8):
+        pl = mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=L)
+        assert pl["kblock"] == L and pl["slots"] >= L
+    with pytest.raises(mmp.MmpError) as e:
+        mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=8)
+    assert e.value.status == -2
+    p = 68719476731  # (2,2): lambda = 131071
+    assert mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=4096)["slots"] == 4096
+    with pytest.raises(mmp.MmpError):
+        mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=100)  # > 16 and not whole stages
+
+
+def test_reserved_options_rejected():
+    o = mmp.MmpOpts()
+    o.reserved[3] = 1
+    out = mmp.MmpPlan()
+    assert mmp.lib().mmp_plan(33554393, 1, 1, 8, 8, 8, ctypes.byref(o), ctypes.byref(out)) == -1
+
+
+def test_footprint_counts_word_copies():
+    p, m, n, k = 1125899906842597, 1000, 700, 300
+    fp = mmp.footprint(p, m, n, k, 2, 2)
+    assert fp == 8 * (m * k + k * n + m * n) + 8 * (2 * m * k + 2 * k * n)
+
+
+def test_argument_errors_before_device_work():
+    lib = mmp.lib()
+    # negative sizes, null pointers with non-empty shapes, bad leading dimension
+    assert lib.mm_modp(33554393, 1, 1, -1, 4, 4, None, None, None) == -1
+    assert lib.mm_modp(33554393, 1, 1, 4, 4, 4, None, None, None) == -1
+    o = mmp.MmpOpts()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.mm_modp_async(ctypes.byref(o), 33554393, 1, 1, 4, 4, 4, fake, 3, ctypes.c_void_p(0x9000), 4,
+                             ctypes.c_void_p(0x20000), 4, None) == -1
+    # C overlapping A
+    assert lib.mm_modp_async(ctypes.byref(o), 33554393, 1, 1, 4, 4, 4, fake, 4, ctypes.c_void_p(0x9000), 4,
+                             ctypes.c_void_p(0x1008), 4, None) == -1
+    # p out of range is rejected by the planner before any launch
+    assert lib.mm_modp(3, 1, 1, 4, 4, 4, fake, ctypes.c_void_p(0x9000), ctypes.c_void_p(0x20000)) == -1
+    # (1,1) at 31 bits has no block size
+    assert lib.mm_modp(2147483647, 1, 1, 4, 4, 4, fake, ctypes.c_void_p(0x9000),
+                       ctypes.c_void_p(0x20000)) == -2
+    # empty products succeed without touching memory
+    assert lib.mm_modp(33554393, 1, 1, 0, 4, 4, None, None, None) == 0
+    assert lib.mm_modp(33554393, 1, 1, 4, 0, 4, None, None, None) == 0
+
+
+# ------------------------------------------------------------------ schedule emulation
+# The kernel accumulates L word products per block, reduces (correction-free
+# when the plan says lazy), and finishes with a complete reduction and the
+# Horner recombination.  This exact-integer emulation of that schedule on
+# worst-case words checks that no partial sum leaves [-2^53, 2^53] for the
+# planner's block, and that the result is the oracle's.
+
+
+def _words(x, a, u):
+    w = []
+    for _ in range(u - 1):
+        w.append(x % a)
+        x //= a
+    w.append(x)
+    return w
+
+
+def _lazy_reduce(x, p):
+    q = 1.0 / p
+    assert abs(x) <= TWO_T
+    c = math.floor(float(x) * q)
+    d = x - c * p
+    assert -p <= d < 2 * p
+    return d
+
+
+def _emulate_entry(p, u, v, L, lazy, arow, bcol):
+    a_, b_ = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+    k = len(arow)
+    acc = [[0] * v for _ in range(u)]
+    peak = 0
+    for i in range(u):
+        for j in range(v):
+            s = 0
+            for l0 in range(0, k, L):
+                for l in range(l0, min(k, l0 + L)):
+                    s += _words(arow[l], a_, u)[i] * _words(bcol[l], b_, v)[j]
+                    peak = max(peak, abs(s))
+                s = _lazy_reduce(s, p) if lazy else s % p
+            acc[i][j] = s % p
+    c = 0
+    for i in reversed(range(u)):
+        si = 0
+        for j in reversed(range(v)):
+            si = (si * b_ + acc[i][j]) % p
+        c = (c * a_ + si) % p
+    return c, peak
+
+
+@pytest.mark.parametrize("p", [33554393, 67108859, 2147483647, 68719476731, 1099511627689,
+                               1125899906842597, 4503599627370449])
+def test_schedule_emulation_worst_case(p):
+    for (u, v) in SUPPORTED:
+        lam = pa.block_size(p, u, v)
+        if lam < 1:
+            continue
+        pl = mmp.plan(p, 64, 64, 64, u, v)
+        L = min(pl["kblock"], 64)
+        a_ = pa.iroot_ceil(p, u)
+        # entries whose words are all large: p - 1 and the largest x < p with low word alpha - 1
+        x_lowmax = ((p - 1) // a_) * a_ - 1 if u > 1 else p - 1
+        for x in {p - 1, x_lowmax}:
+            k = 3 * L + 1
+            arow = [x] * k
+            bcol = [p - 1] * k
+            c, peak = _emulate_entry(p, u, v, L, bool(pl["lazy"]), arow, bcol)
+            assert c == (k * x * (p - 1)) % p
+            assert peak <= TWO_T
