@@ -103,6 +103,8 @@ def main():
     import paper_2601_07508_amd as mmp
 
     prob = gen.config_problems(args.config)[args.variant]
+    if args.form == 2:  # the INT8-digit form takes no word counts
+        prob.u = prob.v = 0
     plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, form=args.form)
     log("workload", prob.tag, "plan", plan)
 

@@ -1,0 +1,319 @@
+// INT8-digit form of C = A B mod p on gfx950 (template; instantiated per
+// digit count by mmp_int8_digits.hip).
+//
+// The paper's closing perspective proposes running the word products in a
+// lower precision with more, narrower words.  Here each entry x of A and B
+// (an integer in [0, p)) is written with D signed base-256 digits,
+//     x' = sum_{i<D} 256^i d_i,   d_i in [-128, 127],   x' = x or x - p,
+// so every digit plane is an int8 matrix.  The D^2 digit products run on the
+// INT8 matrix cores with exact int32 accumulation; products with the same
+// digit weight 256^s (i + j = s) share one accumulator, so there are 2D - 1
+// accumulators per output.  A block of K k-terms keeps every accumulator
+// exact when K * min(D_A, D_B) * 2^14 <= 2^31 - 1 (|d_i d_j| <= 2^14).
+// After each block the accumulators are folded into a binary64 residue:
+//     t = sum_s 256^s D_s mod p  (Horner's rule from the top weight down;
+//         256 t is exact in binary64 and each step is reduced with Alg. 1),
+//     F = F + t mod p,
+// and C = F is written once.  All binary64 steps follow Section 2.1.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "mmp_internal.h"
+
+namespace mmp {
+namespace i8d {
+
+typedef int int4v __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;  // 4 waves, 2 x 2
+constexpr int kBK8 = 64;       // k-bytes per LDS stage (one 16x16x64 MFMA deep)
+constexpr int kRow = kBK8 + 16; // LDS row stride in bytes: 16 lanes' 16-byte reads hit disjoint banks
+
+__device__ __forceinline__ double fmod_full(double x, double p, double q) {
+  const double c = floor(x * q);
+  double d = fma(-c, p, x);
+  d = (d >= p) ? d - p : d;
+  d = (d < 0.0) ? d + p : d;
+  return d;
+}
+
+__device__ __forceinline__ double addmod(double x, double y, double p) {
+  const double s = x + y;
+  return (s >= p) ? s - p : s;
+}
+
+// Signed base-256 digits of x in [0, p): x' = x, or x - p when x exceeds the
+// largest value D digits reach (127 (256^D - 1) / 255); x' is then at least
+// -128 (256^D - 1) / 255 because p <= 256^D.
+template <int D>
+__device__ __forceinline__ void digits_of(double x, int64_t p, int64_t top, int8_t (&d)[D]) {
+  int64_t v = (int64_t)x;
+  if (v > top) v -= p;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int8_t di = (int8_t)(v & 0xff);
+    d[i] = di;
+    v = (v - di) >> 8;
+  }
+}
+
+// A (rows x cols, row-major, ld) -> planes out[D][rows][kp], k zero-padded to kp.
+template <int D>
+__global__ __launch_bounds__(256) void digitize_rows_kernel(const double* __restrict__ X, int64_t rows,
+                                                            int64_t cols, int64_t ld, int64_t kp,
+                                                            int64_t p, int64_t top,
+                                                            int8_t* __restrict__ out) {
+  // each thread: 4 consecutive columns of one row -> one 32-bit store per plane
+  const int64_t quads = kp / 4;
+  const int64_t total = rows * quads;
+  const int64_t plane = rows * kp;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / quads;
+    const int64_t c0 = (t - r * quads) * 4;
+    uint32_t packed[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) packed[i] = 0;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int64_t c = c0 + e;
+      int8_t d[D];
+      if (c < cols) {
+        digits_of<D>(X[r * ld + c], p, top, d);
+      } else {
+#pragma unroll
+        for (int i = 0; i < D; i++) d[i] = 0;
+      }
+#pragma unroll
+      for (int i = 0; i < D; i++) packed[i] |= (uint32_t)(uint8_t)d[i] << (8 * e);
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) *(uint32_t*)(out + i * plane + r * kp + c0) = packed[i];
+  }
+}
+
+// B (krows x ncols, row-major, ld) -> transposed planes out[D][ncols][kp].
+// 64 x 64 tiles through LDS so that both the reads (along n) and the writes
+// (along k) are contiguous.
+template <int D>
+__global__ __launch_bounds__(256) void digitize_cols_kernel(const double* __restrict__ X, int64_t krows,
+                                                            int64_t ncols, int64_t ld, int64_t kp,
+                                                            int64_t p, int64_t top,
+                                                            int8_t* __restrict__ out) {
+  __shared__ uint8_t tile[D][64][64 + 4];
+  const int64_t tiles_n = (ncols + 63) / 64;
+  const int64_t k0 = (int64_t)(blockIdx.x / tiles_n) * 64;
+  const int64_t n0 = (int64_t)(blockIdx.x % tiles_n) * 64;
+  const int tid = threadIdx.x;
+  // read: 64 k-rows x 64 columns, 16 elements per thread
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int kk = e / 64, nn = e % 64;
+    const int64_t row = k0 + kk, col = n0 + nn;
+    int8_t d[D];
+    if (row < krows && col < ncols) {
+      digits_of<D>(X[row * ld + col], p, top, d);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; i++) d[i] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) tile[i][nn][kk] = (uint8_t)d[i];
+  }
+  __syncthreads();
+  // write: for each plane and column, 64 k-bytes as 16 words
+  const int64_t plane = ncols * kp;
+  for (int e = tid; e < D * 64 * 16; e += 256) {
+    const int i = e / (64 * 16);
+    const int rem = e % (64 * 16);
+    const int nn = rem / 16, w = rem % 16;
+    const int64_t col = n0 + nn, kq = k0 + 4 * w;
+    if (col < ncols && kq < kp) {
+      const uint32_t v = (uint32_t)tile[i][nn][4 * w] | ((uint32_t)tile[i][nn][4 * w + 1] << 8) |
+                         ((uint32_t)tile[i][nn][4 * w + 2] << 16) | ((uint32_t)tile[i][nn][4 * w + 3] << 24);
+      *(uint32_t*)(out + i * plane + col * kp + kq) = v;
+    }
+  }
+}
+
+struct GemmArgs {
+  const int8_t* Ad;  // [D][m][kp]
+  const int8_t* Bd;  // [D][n][kp]
+  double* C;
+  int64_t m, n, kp, ldc;
+  double p, q;
+  int64_t stages_per_block;  // LDS stages (64 k-terms each) between folds
+};
+
+__device__ __forceinline__ void tile_coords(int bid, int nb, int nbm, int nbn, int& tmi, int& tni) {
+  const int per = nb / 8, rem = nb % 8, xcd = bid % 8, loc = bid / 8;
+  const int lin = (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+  const int group = 8 * nbn;
+  const int gid = lin / group;
+  const int first = gid * 8;
+  const int gm = min(nbm - first, 8);
+  const int in = lin - gid * group;
+  tmi = first + in % gm;
+  tni = in / gm;
+}
+
+template <int D, int TM, int TN>
+__global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmArgs a) {
+  constexpr int ND = 2 * D - 1;
+  constexpr int BM = 2 * 16 * TM;
+  constexpr int BN = 2 * 16 * TN;
+  constexpr int CHUNKS_A = D * BM * (kBK8 / 16);  // 16-byte chunks per stage
+  constexpr int CHUNKS_B = D * BN * (kBK8 / 16);
+  constexpr int NCA = (CHUNKS_A + kThreads - 1) / kThreads;
+  constexpr int NCB = (CHUNKS_B + kThreads - 1) / kThreads;
+  __shared__ __attribute__((aligned(16))) int8_t As[D][BM][kRow];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[D][BN][kRow];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * TM * 16, wn = (wave & 1) * TN * 16;
+  const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
+  int tmi, tni;
+  tile_coords(blockIdx.x, nbm * nbn, nbm, nbn, tmi, tni);
+  const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
+  const int64_t planeA = a.m * a.kp, planeB = a.n * a.kp;
+
+  int4v pa[NCA], pb[NCB];
+  auto load_stage = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < NCA; e++) {
+      const int c = tid + e * kThreads;
+      const int i = c / (BM * 4), rem = c % (BM * 4), r = rem / 4, q = rem % 4;
+      const int64_t row = m0 + r;
+      pa[e] = (c < CHUNKS_A && row < a.m)
+                  ? *(const int4v*)(a.Ad + i * planeA + row * a.kp + k0 + 16 * q)
+                  : (int4v){0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int e = 0; e < NCB; e++) {
+      const int c = tid + e * kThreads;
+      const int i = c / (BN * 4), rem = c % (BN * 4), r = rem / 4, q = rem % 4;
+      const int64_t col = n0 + r;
+      pb[e] = (c < CHUNKS_B && col < a.n)
+                  ? *(const int4v*)(a.Bd + i * planeB + col * a.kp + k0 + 16 * q)
+                  : (int4v){0, 0, 0, 0};
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < NCA; e++) {
+      const int c = tid + e * kThreads;
+      if (c < CHUNKS_A) {
+        const int i = c / (BM * 4), rem = c % (BM * 4), r = rem / 4, q = rem % 4;
+        *(int4v*)(&As[i][r][16 * q]) = pa[e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NCB; e++) {
+      const int c = tid + e * kThreads;
+      if (c < CHUNKS_B) {
+        const int i = c / (BN * 4), rem = c % (BN * 4), r = rem / 4, q = rem % 4;
+        *(int4v*)(&Bs[i][r][16 * q]) = pb[e];
+      }
+    }
+  };
+
+  int4v acc[ND][TM][TN];
+#pragma unroll
+  for (int s = 0; s < ND; s++)
+#pragma unroll
+    for (int x = 0; x < TM; x++)
+#pragma unroll
+      for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
+  double F[TM][TN][4];
+#pragma unroll
+  for (int x = 0; x < TM; x++)
+#pragma unroll
+    for (int y = 0; y < TN; y++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) F[x][y][r] = 0.0;
+
+  const double p = a.p, q = a.q;
+  // fold the digit-weight accumulators into the binary64 residues and clear them
+  auto fold = [&]() {
+#pragma unroll
+    for (int x = 0; x < TM; x++)
+#pragma unroll
+      for (int y = 0; y < TN; y++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          double t = fmod_full((double)acc[ND - 1][x][y][r], p, q);
+#pragma unroll
+          for (int s = ND - 2; s >= 0; s--) {
+            t = fmod_full(256.0 * t, p, q);                 // 256 t is exact
+            t = fmod_full(t + (double)acc[s][x][y][r], p, q);  // |acc| < 2^31: exact sum
+          }
+          F[x][y][r] = addmod(F[x][y][r], t, p);
+        }
+#pragma unroll
+    for (int s = 0; s < ND; s++)
+#pragma unroll
+      for (int x = 0; x < TM; x++)
+#pragma unroll
+        for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
+  };
+
+  const int64_t nstages = a.kp / kBK8;
+  const int lrow = lane & 15, lk = (lane >> 4) * 16;
+  int64_t in_block = 0;
+  if (nstages > 0) load_stage(0);
+  for (int64_t st = 0; st < nstages; st++) {
+    __syncthreads();
+    store_stage();
+    __syncthreads();
+    if (st + 1 < nstages) load_stage((st + 1) * kBK8);
+
+    int4v bf[D][TN];
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+      for (int y = 0; y < TN; y++) bf[j][y] = *(const int4v*)(&Bs[j][wn + y * 16 + lrow][lk]);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      int4v af[TM];
+#pragma unroll
+      for (int x = 0; x < TM; x++) af[x] = *(const int4v*)(&As[i][wm + x * 16 + lrow][lk]);
+#pragma unroll
+      for (int j = 0; j < D; j++)
+#pragma unroll
+        for (int x = 0; x < TM; x++)
+#pragma unroll
+          for (int y = 0; y < TN; y++)
+            acc[i + j][x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[x], bf[j][y], acc[i + j][x][y], 0, 0, 0);
+    }
+    if (++in_block == a.stages_per_block) {
+      in_block = 0;
+      fold();
+    }
+  }
+  if (in_block != 0) fold();
+
+  // 16x16x64 INT8 MFMA output layout: D[i][j] is value (i & 3) of lane j + 16 (i >> 2).
+#pragma unroll
+  for (int x = 0; x < TM; x++)
+#pragma unroll
+    for (int y = 0; y < TN; y++) {
+      const int64_t col = n0 + wn + y * 16 + lrow;
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
+        if (row < a.m && col < a.n) a.C[row * a.ldc + col] = F[x][y][r] + 0.0;
+      }
+    }
+}
+
+// Tile shape per digit count: accumulator VGPRs = (2D - 1) * TM * TN * 4.
+template <int D>
+struct I8Tile {
+  static constexpr int tm = D <= 2 ? 4 : D <= 4 ? 2 : 2;
+  static constexpr int tn = D <= 2 ? 4 : D <= 4 ? 4 : 2;
+};
+
+}  // namespace i8d
+}  // namespace mmp

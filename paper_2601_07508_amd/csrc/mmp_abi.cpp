@@ -47,6 +47,23 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
+// Stream-ordered workspace: the device's default memory pool, told to keep
+// freed blocks cached so repeated calls do not return memory to the driver.
+std::mutex g_pool_mu;
+std::vector<char> g_pool_ready;
+
+int prepare_pool(int dev) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if ((int)g_pool_ready.size() <= dev) g_pool_ready.resize(dev + 1, 0);
+  if (g_pool_ready[dev]) return 0;
+  hipMemPool_t pool;
+  if (hipError_t e = hipDeviceGetDefaultMemPool(&pool, dev)) return (int)e;
+  uint64_t keep = UINT64_MAX;
+  if (hipError_t e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep)) return (int)e;
+  g_pool_ready[dev] = 1;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -122,6 +139,34 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
         return hip_status(e);
       if (int e = (int)hipStreamSynchronize(s)) return hip_status(e);
       if (host) return MMP_ERANGE;
+    }
+
+    if (pl.form == MMP_FORM_INT8_WORDS) {
+      hipStream_t s = (hipStream_t)stream;
+      int dev = 0;
+      if (int e = (int)hipGetDevice(&dev)) return hip_status(e);
+      if (int e = prepare_pool(dev)) return hip_status(e);
+      void* work = nullptr;
+      if (int e = (int)hipMallocAsync(&work, pl.workspace_bytes, s)) return hip_status(e);
+      mmp::Int8Args g;
+      std::memset(&g, 0, sizeof(g));
+      g.A = A;
+      g.B = B;
+      g.C = C;
+      g.m = m;
+      g.n = n;
+      g.k = k;
+      g.lda = lda;
+      g.ldb = ldb;
+      g.ldc = ldc;
+      g.kp = (k + 63) / 64 * 64;
+      g.p = p;
+      g.q = pl.q;
+      g.kblock = pl.kblock_int8;
+      g.work = (int8_t*)work;
+      int e = mmp::launch_int8_digits(pl.digits_a, g, stream);
+      int e2 = (int)hipFreeAsync(work, s);
+      return hip_status(e ? e : e2);
     }
 
     mmp::Fp64Args a;

@@ -61,6 +61,24 @@ struct Fp64Args {
   int lazy;              // in-loop reductions without corrections
 };
 
+// INT8-digit form: digit planes in a device workspace, then the digit GEMM.
+constexpr int kMaxDigits = 7;  // signed base-256 digits cover p < 2^56
+struct Int8Args {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t m, n, k, lda, ldb, ldc;
+  int64_t kp;        // k rounded up to a multiple of 64 (zero digits beyond k)
+  uint64_t p;
+  double q;
+  int64_t kblock;    // k-terms per int32 accumulation block (multiple of 64)
+  int8_t* work;      // D (m + n) kp bytes
+};
+int digits_for(uint64_t p);                       // ceil(bitsize(p) / 8)
+int64_t int8_kblock(int digits);                  // exact-int32 block length
+size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k);
+int launch_int8_digits(int digits, const Int8Args& a, void* stream);
+
 // Launch the fused FP64-word kernel; returns a hipError_t value (0 = success).
 int launch_fp64_words(int u, int v, int tile_id, const Fp64Args& a, void* stream);
 // Fill a row-major m x n matrix (leading dimension ld) with +0.0.

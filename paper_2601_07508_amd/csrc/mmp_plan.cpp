@@ -104,6 +104,26 @@ KBlock choose_kblock(uint64_t p, int u, int v, int64_t lambda, int64_t k, bool s
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Seconds for the FP64-word kernel: cycles per 16x16 output tile per k-term
+// (block_cost) over 1024 SIMDs at 2.4 GHz.
+double fp64_seconds(int64_t m, int64_t n, int64_t k, int uv, double cost) {
+  const double tiles = (double)cdiv(m, 16) * (double)cdiv(n, 16);
+  return tiles * (double)k * cost * uv / (1024.0 * 2.4e9);
+}
+
+// Seconds for the INT8-digit form: D^2 digit GEMMs at an assumed 60% of the
+// 5 POP/s INT8 peak, two digitizing passes over A and B (8 bytes read, D
+// written per entry, 70% of 8 TB/s), the binary64 folds (about 25 VALU
+// operations per digit weight per output and fold) and three launches.
+double int8_seconds(int64_t m, int64_t n, int64_t k, int d) {
+  const double kp = (double)cdiv(k, 64) * 64.0;
+  const double gemm = (double)d * d * 2.0 * m * n * kp / (0.6 * 5.0e15);
+  const double digitize = (8.0 + d) * ((double)m * k + (double)k * n) / (0.7 * 8.0e12);
+  const double folds = (double)cdiv(k, int8_kblock(d));
+  const double fold = (2.0 * d - 1) * 25.0 * (double)m * n * folds / (64.0 * 1024.0 * 2.4e9 / 4.0);
+  return gemm + digitize + fold + 3 * 4e-6;
+}
+
 int pick_tile(int uv, int64_t m, int64_t n) {
   for (int id = 1; id <= 3; id++) {
     Fp64Tile t = fp64_tile(id, uv);
@@ -114,6 +134,24 @@ int pick_tile(int uv, int64_t m, int64_t n) {
 }
 
 }  // namespace
+
+int digits_for(uint64_t p) {
+  int bits = 0;
+  while (bits < 64 && (p >> bits) != 0) bits++;
+  return (bits + 7) / 8;
+}
+
+int64_t int8_kblock(int digits) {
+  // K min(D_A, D_B) 2^14 <= 2^31 - 1 keeps every int32 accumulator exact
+  const int64_t K = ((int64_t)1 << 31) - 1;
+  const int64_t per = (int64_t)digits << 14;
+  return (K / per) / 64 * 64;
+}
+
+size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k) {
+  const int64_t kp = cdiv(k, 64) * 64;
+  return (size_t)digits * (size_t)(m + n) * (size_t)kp;
+}
 
 int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
          mmp_plan_t* out) {
@@ -128,10 +166,39 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
   if (m < 0 || n < 0 || k < 0) return MMP_EINVAL;
   if ((u == 0) != (v == 0)) return MMP_EINVAL;
   if (u != 0 && !supported_words(u, v)) return MMP_EINVAL;
-  if (o.form != MMP_FORM_AUTO && o.form != MMP_FORM_FP64_WORDS) return MMP_EINVAL;
+  if (o.form != MMP_FORM_AUTO && o.form != MMP_FORM_FP64_WORDS && o.form != MMP_FORM_INT8_WORDS)
+    return MMP_EINVAL;
   if (o.force_kblock < 0 || o.tile < 0 || o.tile > 3) return MMP_EINVAL;
 
   const bool strict = o.strict_fmod != 0;
+
+  // INT8-digit form: asked for, or chosen by cost when neither the words
+  // nor the block are forced.
+  const int d8 = digits_for(p);
+  auto plan_int8 = [&]() {
+    out->p = p;
+    out->u = 0;
+    out->v = 0;
+    out->form = MMP_FORM_INT8_WORDS;
+    out->digits_a = d8;
+    out->digits_b = d8;
+    out->kblock_int8 = int8_kblock(d8);
+    out->q = 1.0 / (double)p;
+    out->bk = 64;
+    out->est_seconds = int8_seconds(m, n, k, d8);
+    out->workspace_bytes = int8_workspace_bytes(d8, m, n, k);
+    return MMP_OK;
+  };
+  if (o.form == MMP_FORM_INT8_WORDS) {
+    if (u != 0 || o.tile != 0) return MMP_EINVAL;
+    int st = plan_int8();
+    if (o.force_kblock != 0) {  // a shorter int32 block, whole 64-term stages
+      if (o.force_kblock % 64 != 0) return MMP_EINVAL;
+      if (o.force_kblock > out->kblock_int8) return MMP_EBOUND;
+      out->kblock_int8 = o.force_kblock;
+    }
+    return st;
+  }
 
   // Candidate word pairs.  With u = v = 0 the planner takes the cheapest by
   // the cost model (uv word products, each at its own block cost), which
@@ -194,10 +261,13 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
   out->bn = fp64_bn(t);
   out->bk = kBK;
   out->q = 1.0 / (double)p;
-  // cycles per 16x16 tile per k-term, over 1024 SIMDs at 2.4 GHz
-  double tiles = (double)cdiv(m, 16) * (double)cdiv(n, 16);
-  out->est_seconds = tiles * (double)k * bk.cost * bu * bv / (1024.0 * 2.4e9);
   out->workspace_bytes = 0;
+  out->est_seconds = fp64_seconds(m, n, k, bu * bv, bk.cost);
+  if (o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0 &&
+      int8_seconds(m, n, k, d8) < out->est_seconds) {
+    std::memset(out, 0, sizeof(*out));
+    return plan_int8();
+  }
   return MMP_OK;
 }
 

@@ -42,6 +42,29 @@ int launch_fp64_words(int u, int v, int tile_id, const Fp64Args& a, void* stream
   return (int)hipErrorInvalidValue;
 }
 
+#define MMP_DECL8(D_) int launch_int8_digits_##D_(const Int8Args& a, void* stream);
+MMP_DECL8(1)
+MMP_DECL8(2)
+MMP_DECL8(3)
+MMP_DECL8(4)
+MMP_DECL8(5)
+MMP_DECL8(6)
+MMP_DECL8(7)
+#undef MMP_DECL8
+
+int launch_int8_digits(int digits, const Int8Args& a, void* stream) {
+  switch (digits) {
+    case 1: return launch_int8_digits_1(a, stream);
+    case 2: return launch_int8_digits_2(a, stream);
+    case 3: return launch_int8_digits_3(a, stream);
+    case 4: return launch_int8_digits_4(a, stream);
+    case 5: return launch_int8_digits_5(a, stream);
+    case 6: return launch_int8_digits_6(a, stream);
+    case 7: return launch_int8_digits_7(a, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
 namespace {
 
 __global__ void zero_fill_kernel(double* C, int64_t m, int64_t n, int64_t ld) {

@@ -1,0 +1,152 @@
+"""GPU parity of the INT8-digit form against the exact oracle (tolerance 0).
+
+The form writes every entry with D = ceil(bitsize(p) / 8) signed base-256
+digits, multiplies digit planes on the INT8 matrix cores with exact int32
+accumulation, and folds the digit weights into a binary64 residue mod p.
+Its result must equal the definition C = A B mod p exactly.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import mmp_inputs as gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mmp = pytest.importorskip("paper_2601_07508_amd")
+
+INT8 = mmp.FORM_INT8_WORDS
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def run(p, A, B, **opts):
+    m, n = A.shape[0], B.shape[1]
+    C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(dev(A), dev(B), C, p, 0, 0, form=INT8, **opts)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+def assert_exact(got, want):
+    w = want.astype(np.float64)
+    bad = np.nonzero(got != w)
+    assert bad[0].size == 0, f"{bad[0].size} mismatches, first at {bad[0][0]},{bad[1][0]}: {got[bad][0]} vs {w[bad][0]}"
+    assert not np.any(np.signbit(got))
+
+
+# one prime per digit count 1..7, plus both sides of byte boundaries
+PRIMES = [5, 251, 257, 65521, 65537, 8388593, 16777213, 2147483647, 4294967291, 68719476731,
+          1099511627689, 281474976710597, 1125899906842597, 4503599627370449]
+SHAPES = [(1, 1, 1), (17, 33, 29), (64, 64, 64), (100, 70, 300), (130, 257, 67), (33, 40, 1000)]
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_int8_parity(p):
+    pl = mmp.plan(p, 64, 64, 64, form=INT8)
+    assert pl["form"] == INT8 and pl["digits_a"] == (p.bit_length() + 7) // 8
+    for (m, n, k) in SHAPES:
+        say("int8", p, m, n, k)
+        A = gen.random_matrix(p + m, 1, m, k, p)
+        B = gen.random_matrix(p + n, 2, k, n, p)
+        assert_exact(run(p, A, B), oracle.mm_modp(p, A, B))
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_int8_worst_case_digits(p):
+    # entries near p - 1, near the centring threshold and at the extremes of
+    # a digit (x = 0x80..80, 0x7f..7f within [0, p))
+    d = (p.bit_length() + 7) // 8
+    cand = [p - 1, p - 2, 0, 1, (p - 1) // 2, (p + 1) // 2]
+    top = int("7f" * d, 16)
+    cand += [x % p for x in (top, top + 1, int("80" * d, 16), int("80" * d, 16) - 1)]
+    vals = np.array(cand, dtype=np.uint64)
+    m, n, k = 24, 20, 333
+    A = vals[np.arange(m * k) % len(vals)].reshape(m, k)
+    B = vals[(np.arange(k * n) * 7 + 3) % len(vals)].reshape(k, n)
+    say("int8 worst", p)
+    assert_exact(run(p, A, B), oracle.mm_modp(p, A, B))
+    Aall = np.full((m, k), p - 1, dtype=np.uint64)
+    assert_exact(run(p, Aall, np.full((k, n), p - 1, dtype=np.uint64)),
+                 oracle.mm_modp(p, Aall, np.full((k, n), p - 1, dtype=np.uint64)))
+
+
+@pytest.mark.parametrize("p", [65521, 2147483647, 1125899906842597, 4503599627370449])
+def test_int8_folds_between_blocks(p):
+    # a short int32 block forces several folds into the binary64 residue
+    m, n, k = 70, 66, 700
+    A = gen.random_matrix(1, 1, m, k, p)
+    B = gen.random_matrix(1, 2, k, n, p)
+    want = oracle.mm_modp(p, A, B)
+    for kb in (64, 128, 192, 640):
+        say("int8 fold", p, kb)
+        assert_exact(run(p, A, B, force_kblock=kb), want)
+
+
+def test_int8_block_bound_is_the_largest_exact_one():
+    for d in range(1, 8):
+        p = gen.prev_prime(1 << (8 * d)) if d < 7 else 4503599627370449
+        kb = mmp.plan(p, 8, 8, 8, form=INT8)["kblock_int8"]
+        assert kb % 64 == 0
+        assert kb * min(d, d) * 2**14 <= 2**31 - 1 < (kb + 64) * d * 2**14
+
+
+def test_int8_full_k_block_with_extreme_digits():
+    # k equal to the block length with every digit product at +2^14:
+    # entries whose digits are all -128 reach the int32 limit exactly.
+    p = 4503599627370449  # 7 digits
+    kb = mmp.plan(p, 8, 8, 8, form=INT8)["kblock_int8"]
+    x = int("80" * 6, 16)  # digits 0x80 = -128 in the low six places
+    x = x % p
+    m, n, k = 16, 16, kb
+    A = np.full((m, k), x, dtype=np.uint64)
+    B = np.full((k, n), x, dtype=np.uint64)
+    say("int8 extreme", kb)
+    assert_exact(run(p, A, B), oracle.mm_modp(p, A, B))
+
+
+def test_int8_strided_and_stream():
+    p = 1099511627689
+    m, n, k = 70, 50, 90
+    A = gen.random_matrix(8, 1, m, k, p)
+    B = gen.random_matrix(8, 2, k, n, p)
+    Ab = torch.zeros((m, k + 13), dtype=torch.float64, device="cuda")
+    Bb = torch.zeros((k, n + 5), dtype=torch.float64, device="cuda")
+    Cb = torch.full((m, n + 9), 7.0, dtype=torch.float64, device="cuda")
+    Ab[:, :k] = dev(A)
+    Bb[:, :n] = dev(B)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    mmp.mm_modp_async(Ab[:, :k], Bb[:, :n], Cb[:, :n], p, stream=s, form=INT8)
+    s.synchronize()
+    out = Cb.cpu().numpy()
+    assert_exact(out[:, :n], oracle.mm_modp(p, A, B))
+    assert np.all(out[:, n:] == 7.0)
+
+
+@pytest.mark.parametrize("p", [8388593, 68719476731, 1125899906842597, 4503599627370449])
+def test_int8_equals_fp64_form(p):
+    m, n, k = 200, 190, 513
+    A = gen.random_matrix(2, 1, m, k, p)
+    B = gen.random_matrix(2, 2, k, n, p)
+    C8 = run(p, A, B)
+    C64 = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(dev(A), dev(B), C64, p, form=mmp.FORM_FP64_WORDS)
+    torch.cuda.synchronize()
+    assert np.array_equal(C8, C64.cpu().numpy())

@@ -101,13 +101,29 @@ def test_plan_invariants(p, uv, k):
 def test_auto_choice_follows_bitsize():
     # Section 3.3: (1,1) for small primes; multiword beyond 26 bits; at 52
     # bits the (2,3)-product (the (2,2) block size is 1 there).
-    assert (mmp.plan(1048573, 1024, 1024, 1024)["u"], mmp.plan(1048573, 1024, 1024, 1024)["v"]) == (1, 1)
+    F = mmp.FORM_FP64_WORDS
+    pl = mmp.plan(1048573, 1024, 1024, 1024, form=F)
+    assert (pl["u"], pl["v"]) == (1, 1)
     for b in range(27, 53):
-        pl = mmp.plan(gen.prev_prime(1 << b), 2048, 2048, 2048)
+        pl = mmp.plan(gen.prev_prime(1 << b), 2048, 2048, 2048, form=F)
         assert pa.block_size(pl["p"], pl["u"], pl["v"]) >= 1
         assert pl["u"] * pl["v"] >= 2
-    pl = mmp.plan(4503599627370449, 2048, 2048, 2048)
+    pl = mmp.plan(4503599627370449, 2048, 2048, 2048, form=F)
     assert pl["u"] * pl["v"] == 6
+
+
+def test_auto_form_choice():
+    # AUTO compares the planner's time estimates of the two forms
+    for b in (20, 25, 36, 50, 52):
+        p = gen.prev_prime(1 << b)
+        pl = mmp.plan(p, 4096, 4096, 4096)
+        f64 = mmp.plan(p, 4096, 4096, 4096, form=mmp.FORM_FP64_WORDS)
+        i8 = mmp.plan(p, 4096, 4096, 4096, form=mmp.FORM_INT8_WORDS)
+        best = mmp.FORM_INT8_WORDS if i8["est_seconds"] < f64["est_seconds"] else mmp.FORM_FP64_WORDS
+        assert pl["form"] == best
+        assert i8["digits_a"] == (b + 7) // 8 and i8["workspace_bytes"] == i8["digits_a"] * 8192 * 4096
+    # explicit words select the FP64 form
+    assert mmp.plan(1125899906842597, 4096, 4096, 4096, 2, 2)["form"] == mmp.FORM_FP64_WORDS
 
 
 def test_auto_orientation_skinny():
