@@ -83,12 +83,15 @@ def cpu_baseline(prob, A, B, budget_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=2, help="workload group 1..4")
     ap.add_argument("--variant", type=int, default=0, help="index inside the workload group")
     ap.add_argument("--form", type=int, default=0, help="0 auto, 1 FP64 words, 2 INT8 digits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the product, time a plain device copy of this many bytes "
+                         "(the reference kernel for scaling HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -101,6 +104,23 @@ def main():
 
     import mmp_inputs as gen
     import paper_2601_07508_amd as mmp
+
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"copy_bytes": args.copy_bytes, "ms": ms,
+                          "GB/s (read+write)": 2 * args.copy_bytes / ms / 1e6}), flush=True)
+        return
 
     prob = gen.config_problems(args.config)[args.variant]
     if args.form == 2:  # the INT8-digit form takes no word counts
@@ -136,6 +156,17 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {t_wall:.3f} s)")
 
+    # per-kernel device time: the library's event pairs around each launch, on
+    # the stream the kernels run on, over the same number of steps
+    mmp.timers_read(reset=True)
+    mmp.timers_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    mmp.timers_enable(False)
+    phases = mmp.timers_read(reset=True)
+    log("phases", phases)
+
     # spot check of the last result against the oracle
     rows = np.array([0, prob.m - 1, prob.m // 2], dtype=np.int64)
     cols = np.array([0, prob.n - 1, prob.n // 3], dtype=np.int64)
@@ -148,19 +179,27 @@ def main():
 
     mnk = float(prob.m) * prob.n * prob.k
     eff = 2.0 * mnk / (ms * 1e-3) / 1e9
-    uv = plan["u"] * plan["v"]
-    word_tflops = 2.0 * uv * mnk / (ms * 1e-3) / 1e12
     digest = source_digest()
     workload = prob.tag
+    if plan["form"] == 1:
+        kernel, phase, peak, unit = "fp64_words_kernel", "fp64_words", FP64_MFMA_PEAK_TFLOPS, "TFLOP/s"
+        work = 2.0 * plan["u"] * plan["v"] * mnk  # word flops per launch
+    else:
+        kernel, phase, peak, unit = "int8_digits_gemm_kernel", "int8_gemm", INT8_MFMA_PEAK_TOPS, "TOP/s"
+        work = 2.0 * plan["digits_a"] * plan["digits_b"] * mnk  # digit-product int8 ops per launch
+    launches, total_ms = phases.get(phase, (0, 0.0))
+    kern_ms = total_ms / max(launches, 1)
+    achieved = work / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
     roofline = {
         "bound": "mfma",
-        "achieved": round(word_tflops, 3),
-        "peak": FP64_MFMA_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(word_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": unit,
+        "frac": round(achieved / peak, 4),
         "traffic": traffic_for(workload, digest),
-        "kernel": "fp64_words_kernel",
-        "algorithmic_flops_per_launch": 2.0 * uv * mnk,
+        "kernel": kernel,
+        "kernel_ms": round(kern_ms, 4),
+        "algorithmic_work_per_launch": work,
     }
     out = {
         "metric": "effective 2mnk GFLOP/s of C=AB mod p",
@@ -180,10 +219,11 @@ def main():
                         f"2^{prob.p.bit_length()}), exact C = AB mod p",
             "m": prob.m, "n": prob.n, "k": prob.k, "p": prob.p, "bits": prob.p.bit_length(),
             "u": plan["u"], "v": plan["v"], "lambda": plan["lambda"], "kblock": plan["kblock"],
+            "digits": plan["digits_a"],
             "form": "fp64_words" if plan["form"] == 1 else "int8_digits", "tile": plan["tile"],
         },
         "roofline": roofline,
-        "mfma_utilization": round(word_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+        "phases_ms_per_step": {k: round(v[1] / max(args.steps, 1), 4) for k, v in phases.items()},
         "source_digest": digest,
     }
     if not args.no_cpu_baseline:

@@ -70,15 +70,23 @@ enum {
 /* Options; a NULL mmp_opts* means all fields zero. */
 typedef struct {
   int form;               /* MMP_FORM_* */
-  int64_t force_kblock;   /* 0: planner's k-block; else the number of k-terms
-                             accumulated between reductions (<= the bound) */
   int validate_entries;   /* 1: check every entry of A and B lies in [0, p)
-                             and is integral before computing (MMP_ERANGE) */
+                             and is integral before computing (MMP_ERANGE);
+                             the call then waits for the check to finish */
   int tile;               /* 0: planner's tile; else a tile id from mmp_plan_t */
   int strict_fmod;        /* 1: every in-loop reduction is the full Alg. 1;
                              0: the planner may use the correction-free form
                              where its range check allows (see mmp_plan_t) */
-  int reserved[7];        /* must be zero */
+  int64_t force_kblock;   /* 0: planner's k-block; else the number of k-terms
+                             accumulated between reductions (<= the bound;
+                             INT8 form: a multiple of 64 up to kblock_int8) */
+  void *workspace;        /* optional caller-owned device workspace; when
+                             NULL the library allocates stream-ordered memory
+                             from the device's default pool.  Pass one (of at
+                             least the queried size) to capture a call into a
+                             HIP graph. */
+  size_t workspace_bytes; /* size of workspace */
+  int reserved[4];        /* must be zero */
 } mmp_opts;
 
 /* What the planner decided for one product (mmp_plan fills it). */
@@ -131,6 +139,119 @@ int mm_modp_async(const mmp_opts *opts, uint64_t p, int u, int v, int64_t m,
                   const double *B, int64_t ldb, double *C, int64_t ldc,
                   void *stream);
 
+/* ---------------------------------------------------------------- batches */
+
+/* count independent products C_i = A_i B_i mod p_i (each job with its own
+ * shape, modulus and words), enqueued on one stream.  Products that share a
+ * kernel configuration run in one launch (up to 16 per launch); no host
+ * synchronisation happens unless validate_entries is set, so with a caller
+ * workspace of mmp_workspace_batched() bytes the call can be captured into a
+ * HIP graph.  The batched block products follow the paper's closing
+ * perspective (Section 6).  Outputs must not overlap each other. */
+int mm_modp_batched(const mmp_job *jobs, int count, const mmp_opts *opts,
+                    void *stream);
+
+/* Device workspace mm_modp_batched needs for these jobs and options (0 if the
+ * jobs are invalid or need none). */
+size_t mmp_workspace_batched(const mmp_job *jobs, int count,
+                             const mmp_opts *opts);
+
+/* Multi-modular product: C[i] = A B mod primes[i] for i < nprimes, for one
+ * integer pair A (m x k), B (k x n) of uint64 entries below 2^entry_bits
+ * (1 <= entry_bits <= 62; DEVICE pointers, row-major, leading dimensions
+ * lda, ldb).  primes is a HOST array of moduli in [5, 2^52); C is a HOST
+ * array of nprimes DEVICE pointers to m x n binary64 outputs (leading
+ * dimension ldc, pairwise disjoint).  This is the multimodular setting the
+ * paper compares against (Section 5.2): with k within one exact int32 block
+ * the integer product's digit-weight sums are formed once on the INT8 matrix
+ * cores and every modulus reduces them (one GEMM launch for up to 64
+ * moduli); otherwise A and B are reduced mod each p on the device and the
+ * products run as a batch.  validate_entries checks the entry bound
+ * (MMP_ERANGE).  Capturable into a graph with a caller workspace of
+ * mmp_workspace_crt() bytes. */
+int mm_modp_crt(const mmp_opts *opts, const uint64_t *A, int64_t lda,
+                const uint64_t *B, int64_t ldb, int64_t m, int64_t n,
+                int64_t k, int entry_bits, const uint64_t *primes,
+                int nprimes, double *const *C, int64_t ldc, void *stream);
+
+/* Device workspace mm_modp_crt needs (0 for invalid arguments). */
+size_t mmp_workspace_crt(int64_t m, int64_t n, int64_t k, int entry_bits,
+                         int nprimes, const mmp_opts *opts);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A request server on one device: products of mixed shapes and moduli are
+ * submitted as they arrive and served with continuous batching.  A
+ * scheduler thread admits queued requests in arrival order while a request
+ * slot is free and the device footprint in flight (mmp_footprint of each
+ * admitted request: operands, result and word or digit copies, per the
+ * storage cost of Section 3.3) stays within hbm_budget; all requests
+ * admitted in one scheduling step are launched together (products sharing a
+ * kernel configuration in one launch) on the least busy of 4 streams, so
+ * requests that arrive while others run start beside them and their work
+ * overlaps on the device.  Results are identical to single calls: every
+ * product is exact. */
+typedef struct mmp_server mmp_server;
+
+enum {
+  MMP_SERVER_DRY_RUN = 1,  /* no device work: each batch completes after the
+                              planner's time estimate; exercises admission,
+                              queueing and latency accounting only (outputs
+                              are not written) */
+  MMP_SUBMIT_NOQUEUE = 1   /* reject with MMP_EBUSY instead of queueing when
+                              the request cannot be admitted at once */
+};
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected;
+  int64_t launches, max_batch;  /* batches launched, largest batch */
+  int64_t queued, running;      /* requests waiting / in flight now */
+  size_t used_bytes, peak_used_bytes, resident_bytes;
+} mmp_server_stats_t;
+
+/* Starts a server on `device` (flags: 0 or MMP_SERVER_DRY_RUN). */
+int mmp_server_create(mmp_server **out, int device, size_t hbm_budget,
+                      int max_slots, int flags);
+
+/* Finishes all queued and running requests, then frees the server, its
+ * streams and resident operands. */
+int mmp_server_destroy(mmp_server *srv);
+
+/* Keeps the INT8 digit planes of a caller-owned matrix resident: side 0
+ * registers an A operand (rows x cols = m x k), side 1 a B operand (k x n),
+ * for modulus p.  A later request whose A (or B) has this pointer, shape,
+ * leading dimension and modulus skips digitising it (the paper's setting of
+ * a fixed A reused across products, Section 4.1).  The planes count against
+ * the budget until mmp_unregister_operand.  The matrix must not change while
+ * registered.  Synchronous. */
+int mmp_register_operand(mmp_server *srv, const double *M, int64_t rows,
+                         int64_t cols, int64_t ld, uint64_t p, int side,
+                         uint64_t *handle);
+
+/* Waits for requests that use the operand, then frees its planes. */
+int mmp_unregister_operand(mmp_server *srv, uint64_t handle);
+
+/* Queues one product (non-blocking); *ticket identifies it.  MMP_ENOMEM if
+ * its footprint can never fit the budget; with MMP_SUBMIT_NOQUEUE,
+ * MMP_EBUSY when it cannot be admitted immediately.  The job's buffers must
+ * stay valid until the ticket is reported done. */
+int mmp_submit(mmp_server *srv, const mmp_job *job, int flags,
+               uint64_t *ticket);
+
+/* *done = 1 when the request has completed; then *status is its result
+ * code and *latency_s the time from submission to completion, and the
+ * ticket is forgotten (a second poll returns MMP_ENOTFOUND). */
+int mmp_poll(mmp_server *srv, uint64_t ticket, int *done, int *status,
+             double *latency_s);
+
+/* Blocks until the request completes (timeout_s < 0: no limit), then reports
+ * as mmp_poll does; MMP_ETIMEOUT if the time runs out first. */
+int mmp_wait(mmp_server *srv, uint64_t ticket, double timeout_s, int *status,
+             double *latency_s);
+
+/* Counters and current occupancy. */
+int mmp_server_stats(mmp_server *srv, mmp_server_stats_t *out);
+
 /* ---------------------------------------------------------------- planning */
 
 /* Fills *out with the plan mm_modp_async would use (host-only; touches no
@@ -149,6 +270,28 @@ const char *mmp_strerror(int status);
 
 /* The hipError_t of the last MMP_EHIP on this thread (0 if none). */
 int mmp_last_hip_error(void);
+
+/* ---------------------------------------------------------------- timers */
+
+/* Per-phase kernel time.  When enabled, every launch the library makes is
+ * bracketed by a HIP event pair on its stream; mmp_timers_read waits for the
+ * recorded events and reports, per phase ("fp64_words", "int8_digitize_a",
+ * "int8_digitize_b", "int8_gemm", ...), the number of launches and their
+ * summed device time.  This measures the paper's time breakdown (Section
+ * 4.2.1) on the device instead of on the host. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} mmp_timer;
+
+/* on = 1 starts recording, 0 stops (already recorded pairs are kept). */
+int mmp_timers_enable(int on);
+
+/* Copies up to cap phase sums into out (cap = 0: only count) and returns the
+ * number of phases; reset = 1 clears the sums afterwards.  Blocks until the
+ * recorded events have completed. */
+int mmp_timers_read(mmp_timer *out, int cap, int reset);
 
 #ifdef __cplusplus
 }

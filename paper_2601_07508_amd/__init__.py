@@ -34,8 +34,8 @@ STATUS = {0: "MMP_OK", -1: "MMP_EINVAL", -2: "MMP_EBOUND", -3: "MMP_ERANGE", -4:
 
 
 class MmpOpts(ctypes.Structure):
-    _fields_ = [("form", _int), ("force_kblock", _i64), ("validate_entries", _int), ("tile", _int),
-                ("strict_fmod", _int), ("reserved", _int * 7)]
+    _fields_ = [("form", _int), ("validate_entries", _int), ("tile", _int), ("strict_fmod", _int),
+                ("force_kblock", _i64), ("workspace", _vp), ("workspace_bytes", _sz), ("reserved", _int * 4)]
 
 
 class MmpPlan(ctypes.Structure):
@@ -71,6 +71,27 @@ _lib.mmp_last_hip_error.argtypes = []
 _lib.mmp_last_hip_error.restype = _int
 
 
+_lib.mm_modp_batched.argtypes = [ctypes.POINTER(MmpJob), _int, ctypes.POINTER(MmpOpts), _vp]
+_lib.mm_modp_batched.restype = _int
+_lib.mmp_workspace_batched.argtypes = [ctypes.POINTER(MmpJob), _int, ctypes.POINTER(MmpOpts)]
+_lib.mmp_workspace_batched.restype = _sz
+_lib.mm_modp_crt.argtypes = [ctypes.POINTER(MmpOpts), _vp, _i64, _vp, _i64, _i64, _i64, _i64, _int,
+                             ctypes.POINTER(_u64), _int, ctypes.POINTER(_vp), _i64, _vp]
+_lib.mm_modp_crt.restype = _int
+_lib.mmp_workspace_crt.argtypes = [_i64, _i64, _i64, _int, _int, ctypes.POINTER(MmpOpts)]
+_lib.mmp_workspace_crt.restype = _sz
+
+
+class MmpTimer(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", _i64), ("total_ms", _dbl)]
+
+
+_lib.mmp_timers_enable.argtypes = [_int]
+_lib.mmp_timers_enable.restype = _int
+_lib.mmp_timers_read.argtypes = [ctypes.POINTER(MmpTimer), _int, _int]
+_lib.mmp_timers_read.restype = _int
+
+
 class MmpError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -85,6 +106,19 @@ def _check(status: int, where: str):
         raise MmpError(status, where)
 
 
+def timers_enable(on: bool = True) -> None:
+    """Start (or stop) recording per-phase kernel times (see mmp_timers_enable)."""
+    _lib.mmp_timers_enable(1 if on else 0)
+
+
+def timers_read(reset: bool = True) -> dict:
+    """{phase: (launches, total_ms)} of the recorded launches; waits for them."""
+    n = _lib.mmp_timers_read(None, 0, 0)
+    buf = (MmpTimer * max(n, 1))()
+    n = _lib.mmp_timers_read(buf, len(buf), 1 if reset else 0)
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(min(n, len(buf)))}
+
+
 def lib() -> ctypes.CDLL:
     """The loaded C library (for tests of the raw C-ABI)."""
     return _lib
@@ -94,13 +128,17 @@ def strerror(status: int) -> str:
     return _lib.mmp_strerror(status).decode()
 
 
-def _opts(form=FORM_AUTO, force_kblock=0, validate_entries=False, tile=0, strict_fmod=False):
+def _opts(form=FORM_AUTO, force_kblock=0, validate_entries=False, tile=0, strict_fmod=False,
+          workspace=None):
     o = MmpOpts()
     o.form = form
     o.force_kblock = force_kblock
     o.validate_entries = 1 if validate_entries else 0
     o.tile = tile
     o.strict_fmod = 1 if strict_fmod else 0
+    if workspace is not None:  # a device tensor owned by the caller
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
     return o
 
 
@@ -172,3 +210,170 @@ def mm_modp_sync(A, B, C, p: int, u: int = 0, v: int = 0):
             raise ValueError("mm_modp needs contiguous matrices")
     _check(_lib.mm_modp(p, u, v, m, n, k, A.data_ptr(), B.data_ptr(), C.data_ptr()), "mm_modp")
     return C
+
+
+def _jobs_array(jobs):
+    """jobs: list of (A, B, C, p, u, v) with float64 CUDA tensors."""
+    arr = (MmpJob * max(len(jobs), 1))()
+    for i, (A, B, C, p, u, v) in enumerate(jobs):
+        for t, name in ((A, "A"), (B, "B"), (C, "C")):
+            _check_mat(t, name)
+        m, k = A.shape
+        k2, n = B.shape
+        if k2 != k or tuple(C.shape) != (m, n):
+            raise ValueError(f"job {i}: shape mismatch")
+        j = arr[i]
+        j.p, j.u, j.v, j.m, j.n, j.k = p, u, v, m, n, k
+        j.A, j.lda = A.data_ptr(), max(A.stride(0), 1)
+        j.B, j.ldb = B.data_ptr(), max(B.stride(0), 1)
+        j.C, j.ldc = C.data_ptr(), max(C.stride(0), 1)
+    return arr
+
+
+def workspace_batched(jobs, **opts) -> int:
+    arr = _jobs_array(jobs)
+    o = _opts(**opts)
+    return int(_lib.mmp_workspace_batched(arr, len(jobs), ctypes.byref(o)))
+
+
+def mm_modp_batched(jobs, stream=None, **opts):
+    """Runs every job (A, B, C, p, u, v) -> C = A B mod p, batched on one stream."""
+    arr = _jobs_array(jobs)
+    o = _opts(**opts)
+    _check(_lib.mm_modp_batched(arr, len(jobs), ctypes.byref(o), _stream_ptr(stream)), "mm_modp_batched")
+
+
+def _check_u64(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype not in (torch.int64, torch.uint64) or not t.is_cuda:
+        raise TypeError(f"{name} must be an int64/uint64 CUDA tensor of non-negative integers")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D tensor with unit column stride")
+
+
+def workspace_crt(m, n, k, entry_bits, nprimes, **opts) -> int:
+    o = _opts(**opts)
+    return int(_lib.mmp_workspace_crt(m, n, k, entry_bits, nprimes, ctypes.byref(o)))
+
+
+def mm_modp_crt(A, B, primes, outs, entry_bits: int, stream=None, **opts):
+    """outs[i] = A B mod primes[i]; A, B int64 CUDA tensors of entries < 2^entry_bits."""
+    _check_u64(A, "A")
+    _check_u64(B, "B")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or len(outs) != len(primes):
+        raise ValueError("shape mismatch")
+    ldc = None
+    for C in outs:
+        _check_mat(C, "C")
+        if tuple(C.shape) != (m, n):
+            raise ValueError("output shape mismatch")
+        if ldc is not None and C.stride(0) != ldc:
+            raise ValueError("outputs must share one leading dimension")
+        ldc = C.stride(0)
+    pr = (_u64 * len(primes))(*primes)
+    cs = (_vp * len(outs))(*[C.data_ptr() for C in outs])
+    o = _opts(**opts)
+    _check(_lib.mm_modp_crt(ctypes.byref(o), A.data_ptr(), max(A.stride(0), 1), B.data_ptr(),
+                            max(B.stride(0), 1), m, n, k, entry_bits, pr, len(primes), cs, max(ldc or n, 1),
+                            _stream_ptr(stream)), "mm_modp_crt")
+
+
+# ------------------------------------------------------------------ serving
+
+class MmpServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("failed", _i64), ("rejected", _i64),
+                ("launches", _i64), ("max_batch", _i64), ("queued", _i64), ("running", _i64),
+                ("used_bytes", _sz), ("peak_used_bytes", _sz), ("resident_bytes", _sz)]
+
+
+SERVER_DRY_RUN = 1
+SUBMIT_NOQUEUE = 1
+
+_lib.mmp_server_create.argtypes = [ctypes.POINTER(_vp), _int, _sz, _int, _int]
+_lib.mmp_server_create.restype = _int
+_lib.mmp_server_destroy.argtypes = [_vp]
+_lib.mmp_server_destroy.restype = _int
+_lib.mmp_register_operand.argtypes = [_vp, _vp, _i64, _i64, _i64, _u64, _int, ctypes.POINTER(_u64)]
+_lib.mmp_register_operand.restype = _int
+_lib.mmp_unregister_operand.argtypes = [_vp, _u64]
+_lib.mmp_unregister_operand.restype = _int
+_lib.mmp_submit.argtypes = [_vp, ctypes.POINTER(MmpJob), _int, ctypes.POINTER(_u64)]
+_lib.mmp_submit.restype = _int
+_lib.mmp_poll.argtypes = [_vp, _u64, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_dbl)]
+_lib.mmp_poll.restype = _int
+_lib.mmp_wait.argtypes = [_vp, _u64, _dbl, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]
+_lib.mmp_wait.restype = _int
+_lib.mmp_server_stats.argtypes = [_vp, ctypes.POINTER(MmpServerStats)]
+_lib.mmp_server_stats.restype = _int
+
+
+class Server:
+    """Continuous-batching request server (see mmp_server_create).
+
+    Tensors passed to submit() are kept referenced until their ticket is
+    reported done, so their memory cannot be released while in flight.
+    """
+
+    def __init__(self, hbm_budget: int, max_slots: int = 64, device: int = 0, dry_run: bool = False):
+        self._h = _vp()
+        _check(_lib.mmp_server_create(ctypes.byref(self._h), device, hbm_budget, max_slots,
+                                      SERVER_DRY_RUN if dry_run else 0), "mmp_server_create")
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            _check(_lib.mmp_server_destroy(self._h), "mmp_server_destroy")
+            self._h = _vp()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def register_operand(self, M, p: int, side: int) -> int:
+        _check_mat(M, "M")
+        h = _u64()
+        _check(_lib.mmp_register_operand(self._h, M.data_ptr(), M.shape[0], M.shape[1], max(M.stride(0), 1),
+                                         p, side, ctypes.byref(h)), "mmp_register_operand")
+        self._keep[("operand", h.value)] = M
+        return h.value
+
+    def unregister_operand(self, handle: int):
+        _check(_lib.mmp_unregister_operand(self._h, handle), "mmp_unregister_operand")
+        self._keep.pop(("operand", handle), None)
+
+    def submit_raw(self, job: MmpJob, noqueue: bool = False, keep=None) -> int:
+        t = _u64()
+        _check(_lib.mmp_submit(self._h, ctypes.byref(job), SUBMIT_NOQUEUE if noqueue else 0, ctypes.byref(t)),
+               "mmp_submit")
+        if keep is not None:
+            self._keep[t.value] = keep
+        return t.value
+
+    def submit(self, A, B, C, p: int, u: int = 0, v: int = 0, noqueue: bool = False) -> int:
+        arr = _jobs_array([(A, B, C, p, u, v)])
+        return self.submit_raw(arr[0], noqueue, keep=(A, B, C))
+
+    def poll(self, ticket: int):
+        """None while running; else (status, latency_s)."""
+        done, st, lat = _int(), _int(), _dbl()
+        _check(_lib.mmp_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(lat)), "mmp_poll")
+        if not done.value:
+            return None
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        st, lat = _int(), _dbl()
+        _check(_lib.mmp_wait(self._h, ticket, timeout_s, ctypes.byref(st), ctypes.byref(lat)), "mmp_wait")
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def stats(self) -> dict:
+        s = MmpServerStats()
+        _check(_lib.mmp_server_stats(self._h, ctypes.byref(s)), "mmp_server_stats")
+        return {f[0]: getattr(s, f[0]) for f in s._fields_}

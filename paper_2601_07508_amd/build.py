@@ -32,7 +32,7 @@ FLAGS = [
 WORD_PAIRS = [(1, 1), (1, 2), (2, 1), (1, 3), (3, 1), (2, 2), (1, 4), (4, 1), (2, 3), (3, 2),
               (2, 4), (4, 2)]
 PER_PAIR = {"mmp_fp64_words.hip"}  # compiled once per word pair
-PER_DIGITS = {"mmp_int8_digits.hip"}  # compiled once per digit count 1..7
+PER_DIGITS = {"mmp_int8_digits.hip"}  # compiled once per digit count 1..8
 
 
 def sources():
@@ -45,7 +45,7 @@ def sources():
             for u, v in WORD_PAIRS:
                 out.append((src, [f"-DMMP_U={u}", f"-DMMP_V={v}"], f"{base}.{u}{v}.o"))
         elif base in PER_DIGITS:
-            for d in range(1, 8):
+            for d in range(1, 9):
                 out.append((src, [f"-DMMP_D={d}"], f"{base}.{d}.o"))
         else:
             out.append((src, [], base + ".o"))

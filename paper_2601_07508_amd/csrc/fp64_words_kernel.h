@@ -101,8 +101,13 @@ __device__ __forceinline__ void tile_coords(int bid, int nb, int nbm, int nbn, i
 }
 
 template <int U, int V, int TM, int TN, int FE>
-__global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Args a) {
+__global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt) {
   static_assert(FE == 1 || FE == 2 || FE == 4, "reduction period");
+  // which product of the batch this workgroup belongs to (uniform, scalar)
+  int job = 0;
+  while (job + 1 < bt.njobs && (int)blockIdx.x >= bt.tile_start[job + 1]) job++;
+  const Fp64Args& a = bt.job[job];
+  const int local_bid = (int)blockIdx.x - bt.tile_start[job];
   constexpr int BM = 2 * TM * 16;
   constexpr int BN = 2 * TN * 16;
   constexpr int LDA = kBK + kPadA;
@@ -121,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Args a) 
   const int nbm = (int)((a.m + BM - 1) / BM);
   const int nbn = (int)((a.n + BN - 1) / BN);
   int tmi, tni;
-  tile_coords(blockIdx.x, nbm * nbn, nbm, nbn, tmi, tni);
+  tile_coords(local_bid, nbm * nbn, nbm, nbn, tmi, tni);
   const int64_t m0 = (int64_t)tmi * BM;
   const int64_t n0 = (int64_t)tni * BN;
 
@@ -308,15 +313,31 @@ struct TileOf {
   static constexpr int tn = fp64_tile_c(ID, UV).tn;
 };
 
+// Tiles of one product for a given shape.
+template <int BM, int BN>
+inline int64_t tiles_of(const Fp64Args& a) {
+  return ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN);
+}
+
 template <int U, int V, int ID, int FE>
-int launch_shape(const Fp64Args& a, hipStream_t s) {
+int launch_shape(const Fp64Batch& b0, hipStream_t s) {
   constexpr int TM = TileOf<U * V, ID>::tm, TN = TileOf<U * V, ID>::tn;
   constexpr int BM = 2 * 16 * TM, BN = 2 * 16 * TN;
-  const int64_t nb = ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN);
-  if (nb <= 0) return 0;
-  if (nb > 0x7fffffff) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL((fp64_words_kernel<U, V, TM, TN, FE>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
-  return (int)hipGetLastError();
+  Fp64Batch b = b0;
+  int64_t total = 0;
+  for (int j = 0; j < b.njobs; j++) {
+    b.tile_start[j] = (int)total;
+    total += tiles_of<BM, BN>(b.job[j]);
+    if (total > 0x7fffffff) return (int)hipErrorInvalidValue;
+  }
+  b.tile_start[b.njobs] = (int)total;
+  if (total <= 0) return 0;
+  TimerTok* t = timer_begin("fp64_words");
+  hipExtLaunchKernelGGL((fp64_words_kernel<U, V, TM, TN, FE>), dim3((unsigned)total), dim3(kThreads), 0, s,
+                        timer_start(t), timer_stop(t), 0, b);
+  const int e = (int)hipGetLastError();
+  timer_commit(t, e);
+  return e;
 }
 
 }  // namespace fp64w

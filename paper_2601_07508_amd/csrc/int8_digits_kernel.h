@@ -45,13 +45,11 @@ __device__ __forceinline__ double addmod(double x, double y, double p) {
   return (s >= p) ? s - p : s;
 }
 
-// Signed base-256 digits of x in [0, p): x' = x, or x - p when x exceeds the
-// largest value D digits reach (127 (256^D - 1) / 255); x' is then at least
-// -128 (256^D - 1) / 255 because p <= 256^D.
+// Signed base-256 digits of an integer v with -128 R <= v <= 127 R,
+// R = (256^D - 1) / 255: the low byte read as int8 is the digit, and the
+// exact quotient (v - d) / 256 carries on.
 template <int D>
-__device__ __forceinline__ void digits_of(double x, int64_t p, int64_t top, int8_t (&d)[D]) {
-  int64_t v = (int64_t)x;
-  if (v > top) v -= p;
+__device__ __forceinline__ void digits_of_int(int64_t v, int8_t (&d)[D]) {
 #pragma unroll
   for (int i = 0; i < D; i++) {
     const int8_t di = (int8_t)(v & 0xff);
@@ -60,12 +58,26 @@ __device__ __forceinline__ void digits_of(double x, int64_t p, int64_t top, int8
   }
 }
 
+// Entry loaders.  Residues: x in [0, p) stored as binary64; the digits are
+// those of x' = x, or x - p when x exceeds 127 R (then x' >= -128 R because
+// p <= 256^D).  Integers: uint64 entries below 2^62, taken as they are.
+struct ResidueIn {
+  const double* X;
+  int64_t p, top;
+  __device__ __forceinline__ int64_t operator()(int64_t idx) const {
+    int64_t v = (int64_t)X[idx];
+    return v > top ? v - p : v;
+  }
+};
+struct IntegerIn {
+  const uint64_t* X;
+  __device__ __forceinline__ int64_t operator()(int64_t idx) const { return (int64_t)X[idx]; }
+};
+
 // A (rows x cols, row-major, ld) -> planes out[D][rows][kp], k zero-padded to kp.
-template <int D>
-__global__ __launch_bounds__(256) void digitize_rows_kernel(const double* __restrict__ X, int64_t rows,
-                                                            int64_t cols, int64_t ld, int64_t kp,
-                                                            int64_t p, int64_t top,
-                                                            int8_t* __restrict__ out) {
+template <int D, class In>
+__global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, int64_t cols, int64_t ld,
+                                                            int64_t kp, int8_t* __restrict__ out) {
   // each thread: 4 consecutive columns of one row -> one 32-bit store per plane
   const int64_t quads = kp / 4;
   const int64_t total = rows * quads;
@@ -82,7 +94,7 @@ __global__ __launch_bounds__(256) void digitize_rows_kernel(const double* __rest
       const int64_t c = c0 + e;
       int8_t d[D];
       if (c < cols) {
-        digits_of<D>(X[r * ld + c], p, top, d);
+        digits_of_int<D>(X(r * ld + c), d);
       } else {
 #pragma unroll
         for (int i = 0; i < D; i++) d[i] = 0;
@@ -98,11 +110,9 @@ __global__ __launch_bounds__(256) void digitize_rows_kernel(const double* __rest
 // B (krows x ncols, row-major, ld) -> transposed planes out[D][ncols][kp].
 // 64 x 64 tiles through LDS so that both the reads (along n) and the writes
 // (along k) are contiguous.
-template <int D>
-__global__ __launch_bounds__(256) void digitize_cols_kernel(const double* __restrict__ X, int64_t krows,
-                                                            int64_t ncols, int64_t ld, int64_t kp,
-                                                            int64_t p, int64_t top,
-                                                            int8_t* __restrict__ out) {
+template <int D, class In>
+__global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows, int64_t ncols, int64_t ld,
+                                                            int64_t kp, int8_t* __restrict__ out) {
   __shared__ uint8_t tile[D][64][64 + 4];
   const int64_t tiles_n = (ncols + 63) / 64;
   const int64_t k0 = (int64_t)(blockIdx.x / tiles_n) * 64;
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(256) void digitize_cols_kernel(const double* __rest
     const int64_t row = k0 + kk, col = n0 + nn;
     int8_t d[D];
     if (row < krows && col < ncols) {
-      digits_of<D>(X[row * ld + col], p, top, d);
+      digits_of_int<D>(X(row * ld + col), d);
     } else {
 #pragma unroll
       for (int i = 0; i < D; i++) d[i] = 0;
@@ -159,25 +169,39 @@ __device__ __forceinline__ void tile_coords(int bid, int nb, int nbm, int nbn, i
   tni = in / gm;
 }
 
-template <int D, int TM, int TN>
-__global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmArgs a) {
-  constexpr int ND = 2 * D - 1;
-  constexpr int BM = 2 * 16 * TM;
-  constexpr int BN = 2 * 16 * TN;
+struct GemmBatch {
+  int njobs;
+  int tile_start[kMaxBatch + 1];
+  GemmArgs job[kMaxBatch];
+};
+
+// LDS planes of one stage: D digit planes of a BM x 64 slab of A and of a
+// BN x 64 slab of B^T, rows padded to kRow bytes.
+template <int D, int BM, int BN>
+struct DigitStage {
+  int8_t A[D][BM][kRow];
+  int8_t B[D][BN][kRow];
+};
+
+// The digit-product loop of one BM x BN tile: for every LDS stage of 64
+// k-terms, all D^2 digit products on 16x16x64 INT8 MFMAs into the 2D - 1
+// digit-weight accumulators; fold() runs after every stages_per_block stages
+// and once at the end if the last block is partial.
+template <int D, int TM, int TN, class Fold>
+__device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, const int8_t* __restrict__ Bd,
+                                                int64_t m, int64_t n, int64_t kp, int64_t m0, int64_t n0,
+                                                int64_t stages_per_block,
+                                                DigitStage<D, 32 * TM, 32 * TN>& sm,
+                                                int4v (&acc)[2 * D - 1][TM][TN], Fold fold) {
+  constexpr int BM = 32 * TM;
+  constexpr int BN = 32 * TN;
   constexpr int CHUNKS_A = D * BM * (kBK8 / 16);  // 16-byte chunks per stage
   constexpr int CHUNKS_B = D * BN * (kBK8 / 16);
   constexpr int NCA = (CHUNKS_A + kThreads - 1) / kThreads;
   constexpr int NCB = (CHUNKS_B + kThreads - 1) / kThreads;
-  __shared__ __attribute__((aligned(16))) int8_t As[D][BM][kRow];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[D][BN][kRow];
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * TM * 16, wn = (wave & 1) * TN * 16;
-  const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
-  int tmi, tni;
-  tile_coords(blockIdx.x, nbm * nbn, nbm, nbn, tmi, tni);
-  const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
-  const int64_t planeA = a.m * a.kp, planeB = a.n * a.kp;
+  const int64_t planeA = m * kp, planeB = n * kp;
 
   int4v pa[NCA], pb[NCB];
   auto load_stage = [&](int64_t k0) {
@@ -186,18 +210,16 @@ __global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmAr
       const int c = tid + e * kThreads;
       const int i = c / (BM * 4), rem = c % (BM * 4), r = rem / 4, q = rem % 4;
       const int64_t row = m0 + r;
-      pa[e] = (c < CHUNKS_A && row < a.m)
-                  ? *(const int4v*)(a.Ad + i * planeA + row * a.kp + k0 + 16 * q)
-                  : (int4v){0, 0, 0, 0};
+      pa[e] = (c < CHUNKS_A && row < m) ? *(const int4v*)(Ad + i * planeA + row * kp + k0 + 16 * q)
+                                       : (int4v){0, 0, 0, 0};
     }
 #pragma unroll
     for (int e = 0; e < NCB; e++) {
       const int c = tid + e * kThreads;
       const int i = c / (BN * 4), rem = c % (BN * 4), r = rem / 4, q = rem % 4;
       const int64_t col = n0 + r;
-      pb[e] = (c < CHUNKS_B && col < a.n)
-                  ? *(const int4v*)(a.Bd + i * planeB + col * a.kp + k0 + 16 * q)
-                  : (int4v){0, 0, 0, 0};
+      pb[e] = (c < CHUNKS_B && col < n) ? *(const int4v*)(Bd + i * planeB + col * kp + k0 + 16 * q)
+                                       : (int4v){0, 0, 0, 0};
     }
   };
   auto store_stage = [&]() {
@@ -206,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmAr
       const int c = tid + e * kThreads;
       if (c < CHUNKS_A) {
         const int i = c / (BM * 4), rem = c % (BM * 4), r = rem / 4, q = rem % 4;
-        *(int4v*)(&As[i][r][16 * q]) = pa[e];
+        *(int4v*)(&sm.A[i][r][16 * q]) = pa[e];
       }
     }
 #pragma unroll
@@ -214,10 +236,64 @@ __global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmAr
       const int c = tid + e * kThreads;
       if (c < CHUNKS_B) {
         const int i = c / (BN * 4), rem = c % (BN * 4), r = rem / 4, q = rem % 4;
-        *(int4v*)(&Bs[i][r][16 * q]) = pb[e];
+        *(int4v*)(&sm.B[i][r][16 * q]) = pb[e];
       }
     }
   };
+
+  const int64_t nstages = kp / kBK8;
+  const int lrow = lane & 15, lk = (lane >> 4) * 16;
+  int64_t in_block = 0;
+  if (nstages > 0) load_stage(0);
+  for (int64_t st = 0; st < nstages; st++) {
+    __syncthreads();
+    store_stage();
+    __syncthreads();
+    if (st + 1 < nstages) load_stage((st + 1) * kBK8);
+
+    int4v bf[D][TN];
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+      for (int y = 0; y < TN; y++) bf[j][y] = *(const int4v*)(&sm.B[j][wn + y * 16 + lrow][lk]);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      int4v af[TM];
+#pragma unroll
+      for (int x = 0; x < TM; x++) af[x] = *(const int4v*)(&sm.A[i][wm + x * 16 + lrow][lk]);
+#pragma unroll
+      for (int j = 0; j < D; j++)
+#pragma unroll
+        for (int x = 0; x < TM; x++)
+#pragma unroll
+          for (int y = 0; y < TN; y++)
+            acc[i + j][x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[x], bf[j][y], acc[i + j][x][y], 0, 0, 0);
+    }
+    if (++in_block == stages_per_block) {
+      in_block = 0;
+      fold();
+    }
+  }
+  if (in_block != 0) fold();
+}
+
+template <int D, int TM, int TN>
+__global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmBatch bt) {
+  constexpr int ND = 2 * D - 1;
+  constexpr int BM = 32 * TM;
+  constexpr int BN = 32 * TN;
+  __shared__ __attribute__((aligned(16))) DigitStage<D, BM, BN> sm;
+
+  int job = 0;
+  while (job + 1 < bt.njobs && (int)blockIdx.x >= bt.tile_start[job + 1]) job++;
+  const GemmArgs& a = bt.job[job];
+  const int local_bid = (int)blockIdx.x - bt.tile_start[job];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * TM * 16, wn = (wave & 1) * TN * 16;
+  const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
+  int tmi, tni;
+  tile_coords(local_bid, nbm * nbn, nbm, nbn, tmi, tni);
+  const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
 
   int4v acc[ND][TM][TN];
 #pragma unroll
@@ -246,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmAr
           double t = fmod_full((double)acc[ND - 1][x][y][r], p, q);
 #pragma unroll
           for (int s = ND - 2; s >= 0; s--) {
-            t = fmod_full(256.0 * t, p, q);                 // 256 t is exact
+            t = fmod_full(256.0 * t, p, q);                    // 256 t is exact
             t = fmod_full(t + (double)acc[s][x][y][r], p, q);  // |acc| < 2^31: exact sum
           }
           F[x][y][r] = addmod(F[x][y][r], t, p);
@@ -258,43 +334,10 @@ __global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmAr
 #pragma unroll
         for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
   };
-
-  const int64_t nstages = a.kp / kBK8;
-  const int lrow = lane & 15, lk = (lane >> 4) * 16;
-  int64_t in_block = 0;
-  if (nstages > 0) load_stage(0);
-  for (int64_t st = 0; st < nstages; st++) {
-    __syncthreads();
-    store_stage();
-    __syncthreads();
-    if (st + 1 < nstages) load_stage((st + 1) * kBK8);
-
-    int4v bf[D][TN];
-#pragma unroll
-    for (int j = 0; j < D; j++)
-#pragma unroll
-      for (int y = 0; y < TN; y++) bf[j][y] = *(const int4v*)(&Bs[j][wn + y * 16 + lrow][lk]);
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-      int4v af[TM];
-#pragma unroll
-      for (int x = 0; x < TM; x++) af[x] = *(const int4v*)(&As[i][wm + x * 16 + lrow][lk]);
-#pragma unroll
-      for (int j = 0; j < D; j++)
-#pragma unroll
-        for (int x = 0; x < TM; x++)
-#pragma unroll
-          for (int y = 0; y < TN; y++)
-            acc[i + j][x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[x], bf[j][y], acc[i + j][x][y], 0, 0, 0);
-    }
-    if (++in_block == a.stages_per_block) {
-      in_block = 0;
-      fold();
-    }
-  }
-  if (in_block != 0) fold();
+  digit_tile_loop<D, TM, TN>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.stages_per_block, sm, acc, fold);
 
   // 16x16x64 INT8 MFMA output layout: D[i][j] is value (i & 3) of lane j + 16 (i >> 2).
+  const int lrow = lane & 15;
 #pragma unroll
   for (int x = 0; x < TM; x++)
 #pragma unroll
@@ -308,10 +351,72 @@ __global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmAr
     }
 }
 
+// Multi-modular product: one integer pair A, B against many moduli.  The
+// digit products of the integers are formed once (k within one int32 block)
+// and every modulus reduces the same digit-weight sums in the epilogue:
+// C_i = sum_s 256^s D_s mod p_i.
+constexpr int kMaxPrimes = 64;
+struct CrtArgs {
+  const int8_t* Ad;  // [D][m][kp]
+  const int8_t* Bd;  // [D][n][kp]
+  int64_t m, n, kp, ldc;
+  int nprimes;
+  double p[kMaxPrimes];
+  double q[kMaxPrimes];
+  double* C[kMaxPrimes];
+};
+
+template <int D, int TM, int TN>
+__global__ __launch_bounds__(kThreads) void crt_gemm_kernel(const CrtArgs a) {
+  constexpr int ND = 2 * D - 1;
+  constexpr int BM = 32 * TM;
+  constexpr int BN = 32 * TN;
+  __shared__ __attribute__((aligned(16))) DigitStage<D, BM, BN> sm;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * TM * 16, wn = (wave & 1) * TN * 16;
+  const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
+  int tmi, tni;
+  tile_coords(blockIdx.x, nbm * nbn, nbm, nbn, tmi, tni);
+  const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
+
+  int4v acc[ND][TM][TN];
+#pragma unroll
+  for (int s = 0; s < ND; s++)
+#pragma unroll
+    for (int x = 0; x < TM; x++)
+#pragma unroll
+      for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
+  // one int32 block covers the whole k (checked by the launcher)
+  digit_tile_loop<D, TM, TN>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.kp / kBK8 + 1, sm, acc, [] {});
+
+  const int lrow = lane & 15;
+  for (int pi = 0; pi < a.nprimes; pi++) {
+    const double p = a.p[pi], q = a.q[pi];
+    double* C = a.C[pi];
+#pragma unroll
+    for (int x = 0; x < TM; x++)
+#pragma unroll
+      for (int y = 0; y < TN; y++) {
+        const int64_t col = n0 + wn + y * 16 + lrow;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          double t = fmod_full((double)acc[ND - 1][x][y][r], p, q);
+#pragma unroll
+          for (int s = ND - 2; s >= 0; s--) {
+            t = fmod_full(256.0 * t, p, q);
+            t = fmod_full(t + (double)acc[s][x][y][r], p, q);
+          }
+          const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
+          if (row < a.m && col < a.n) C[row * a.ldc + col] = t + 0.0;
+        }
+      }
+  }
+}
+
 // Tile shape per digit count: accumulator VGPRs = (2D - 1) * TM * TN * 4.
 template <int D>
 struct I8Tile {
-  static constexpr int tm = D <= 2 ? 4 : D <= 4 ? 2 : 2;
+  static constexpr int tm = D <= 2 ? 4 : 2;
   static constexpr int tn = D <= 2 ? 4 : D <= 4 ? 4 : 2;
 };
 

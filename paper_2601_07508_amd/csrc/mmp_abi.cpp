@@ -10,14 +10,21 @@
 #include "mmp_internal.h"
 
 namespace {
-
 thread_local int g_last_hip_error = 0;
+}  // namespace
+
+namespace mmp {
 
 int hip_status(int err) {
   if (err == 0) return MMP_OK;
   g_last_hip_error = err;
   return err == (int)hipErrorOutOfMemory ? MMP_ENOMEM : MMP_EHIP;
 }
+
+}  // namespace mmp
+
+namespace {
+using mmp::hip_status;
 
 // One device int per device for entry validation.
 std::mutex g_flag_mu;
@@ -34,6 +41,10 @@ int* validation_flag(int dev) {
   return g_flags[dev];
 }
 
+}  // namespace
+
+namespace mmp {
+
 bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
   const char* x = (const char*)a;
   const char* y = (const char*)b;
@@ -47,10 +58,23 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
+int check_product_args(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, const double* C, int64_t ldc) {
+  if (m < 0 || n < 0 || k < 0) return MMP_EINVAL;
+  if (m > 0 && n > 0) {
+    if (!C || ldc < n) return MMP_EINVAL;
+    if (k > 0 && (!A || !B || lda < k || ldb < n)) return MMP_EINVAL;
+    if (k > 0 && (ranges_overlap(C, span_bytes(m, n, ldc), A, span_bytes(m, k, lda)) ||
+                  ranges_overlap(C, span_bytes(m, n, ldc), B, span_bytes(k, n, ldb))))
+      return MMP_EINVAL;
+  }
+  return MMP_OK;
+}
+
 // Stream-ordered workspace: the device's default memory pool, told to keep
 // freed blocks cached so repeated calls do not return memory to the driver.
-std::mutex g_pool_mu;
-std::vector<char> g_pool_ready;
+static std::mutex g_pool_mu;
+static std::vector<char> g_pool_ready;
 
 int prepare_pool(int dev) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -63,6 +87,113 @@ int prepare_pool(int dev) {
   g_pool_ready[dev] = 1;
   return 0;
 }
+
+int acquire_workspace(size_t bytes, const mmp_opts* opts, void* stream, void** out, bool* owned) {
+  *out = nullptr;
+  *owned = false;
+  if (bytes == 0) return MMP_OK;
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < bytes) return MMP_EINVAL;
+    *out = opts->workspace;
+    return MMP_OK;
+  }
+  int dev = 0;
+  if (int e = (int)hipGetDevice(&dev)) return hip_status(e);
+  if (int e = prepare_pool(dev)) return hip_status(e);
+  if (int e = (int)hipMallocAsync(out, bytes, (hipStream_t)stream)) return hip_status(e);
+  *owned = true;
+  return MMP_OK;
+}
+
+int release_workspace(void* ptr, bool owned, void* stream) {
+  if (!owned || !ptr) return MMP_OK;
+  return hip_status((int)hipFreeAsync(ptr, (hipStream_t)stream));
+}
+
+int validate_product_entries(uint64_t p, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, void* stream) {
+  int dev = 0;
+  if (int e = (int)hipGetDevice(&dev)) return hip_status(e);
+  int* flag = validation_flag(dev);
+  if (!flag) return MMP_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  if (int e = (int)hipMemsetAsync(flag, 0, sizeof(int), s)) return hip_status(e);
+  if (int e = launch_validate(A, m, k, lda, (double)p, flag, stream)) return hip_status(e);
+  if (int e = launch_validate(B, k, n, ldb, (double)p, flag, stream)) return hip_status(e);
+  int host = 0;
+  if (int e = (int)hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s)) return hip_status(e);
+  if (int e = (int)hipStreamSynchronize(s)) return hip_status(e);
+  return host ? MMP_ERANGE : MMP_OK;
+}
+
+int validate_integer_entries(int bits, int64_t m, int64_t n, int64_t k, const uint64_t* A, int64_t lda,
+                             const uint64_t* B, int64_t ldb, void* stream) {
+  int dev = 0;
+  if (int e = (int)hipGetDevice(&dev)) return hip_status(e);
+  int* flag = validation_flag(dev);
+  if (!flag) return MMP_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  if (int e = (int)hipMemsetAsync(flag, 0, sizeof(int), s)) return hip_status(e);
+  if (int e = launch_validate_bits(A, m, k, lda, bits, flag, stream)) return hip_status(e);
+  if (int e = launch_validate_bits(B, k, n, ldb, bits, flag, stream)) return hip_status(e);
+  int host = 0;
+  if (int e = (int)hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s)) return hip_status(e);
+  if (int e = (int)hipStreamSynchronize(s)) return hip_status(e);
+  return host ? MMP_ERANGE : MMP_OK;
+}
+
+Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double* C, int64_t ldc) {
+  Fp64Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.A = A;
+  a.B = B;
+  a.C = C;
+  a.m = m;
+  a.n = n;
+  a.k = k;
+  a.lda = lda;
+  a.ldb = ldb;
+  a.ldc = ldc;
+  a.p = (double)pl.p;
+  a.q = pl.q;
+  a.alpha = (double)pl.alpha;
+  a.beta = (double)pl.beta;
+  a.ainv = (pl.u > 1 && is_pow2(pl.alpha)) ? 1.0 / (double)pl.alpha : 0.0;
+  a.binv = (pl.v > 1 && is_pow2(pl.beta)) ? 1.0 / (double)pl.beta : 0.0;
+  a.L = (int)pl.kblock;
+  a.S = pl.slots;
+  a.KR = (pl.slots <= kBK) ? (kBK / pl.slots) * (int)pl.kblock : kBK;
+  a.stages_per_block = pl.slots >= kBK ? pl.slots / kBK : 1;
+  a.lazy = pl.lazy;
+  return a;
+}
+
+Int8Args make_int8_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double* C, int64_t ldc, int8_t* work) {
+  Int8Args g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.kp = (k + 63) / 64 * 64;
+  g.p = pl.p;
+  g.q = pl.q;
+  g.kblock = pl.kblock_int8;
+  g.work = work;
+  return g;
+}
+
+}  // namespace mmp
+
+namespace {
+using namespace mmp;
 
 }  // namespace
 
@@ -111,87 +242,30 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
                   const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                   void* stream) {
   try {
-    if (m < 0 || n < 0 || k < 0) return MMP_EINVAL;
-    if (m > 0 && n > 0) {
-      if (!C || ldc < n) return MMP_EINVAL;
-      if (k > 0 && (!A || !B || lda < k || ldb < n)) return MMP_EINVAL;
-      if (k > 0 && (ranges_overlap(C, span_bytes(m, n, ldc), A, span_bytes(m, k, lda)) ||
-                    ranges_overlap(C, span_bytes(m, n, ldc), B, span_bytes(k, n, ldb))))
-        return MMP_EINVAL;
-    }
+    if (int st = check_product_args(m, n, k, A, lda, B, ldb, C, ldc)) return st;
     mmp_plan_t pl;
-    int st = mmp::plan(p, u, v, m, n, k, opts, &pl);
-    if (st != MMP_OK) return st;
+    if (int st = mmp::plan(p, u, v, m, n, k, opts, &pl)) return st;
     if (m == 0 || n == 0) return MMP_OK;
-    if (k == 0) return hip_status(mmp::launch_zero_fill(C, m, n, ldc, stream));
-
-    if (opts && opts->validate_entries) {
-      int dev = 0;
-      if (int e = (int)hipGetDevice(&dev)) return hip_status(e);
-      int* flag = validation_flag(dev);
-      if (!flag) return MMP_ENOMEM;
-      hipStream_t s = (hipStream_t)stream;
-      if (int e = (int)hipMemsetAsync(flag, 0, sizeof(int), s)) return hip_status(e);
-      if (int e = mmp::launch_validate(A, m, k, lda, (double)p, flag, stream)) return hip_status(e);
-      if (int e = mmp::launch_validate(B, k, n, ldb, (double)p, flag, stream)) return hip_status(e);
-      int host = 0;
-      if (int e = (int)hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s))
-        return hip_status(e);
-      if (int e = (int)hipStreamSynchronize(s)) return hip_status(e);
-      if (host) return MMP_ERANGE;
-    }
+    if (k == 0) return hip_status(launch_zero_fill(C, m, n, ldc, stream));
+    if (opts && opts->validate_entries)
+      if (int st = validate_product_entries(p, m, n, k, A, lda, B, ldb, stream)) return st;
 
     if (pl.form == MMP_FORM_INT8_WORDS) {
-      hipStream_t s = (hipStream_t)stream;
-      int dev = 0;
-      if (int e = (int)hipGetDevice(&dev)) return hip_status(e);
-      if (int e = prepare_pool(dev)) return hip_status(e);
       void* work = nullptr;
-      if (int e = (int)hipMallocAsync(&work, pl.workspace_bytes, s)) return hip_status(e);
-      mmp::Int8Args g;
-      std::memset(&g, 0, sizeof(g));
-      g.A = A;
-      g.B = B;
-      g.C = C;
-      g.m = m;
-      g.n = n;
-      g.k = k;
-      g.lda = lda;
-      g.ldb = ldb;
-      g.ldc = ldc;
-      g.kp = (k + 63) / 64 * 64;
-      g.p = p;
-      g.q = pl.q;
-      g.kblock = pl.kblock_int8;
-      g.work = (int8_t*)work;
-      int e = mmp::launch_int8_digits(pl.digits_a, g, stream);
-      int e2 = (int)hipFreeAsync(work, s);
-      return hip_status(e ? e : e2);
+      bool owned = false;
+      if (int st = acquire_workspace(pl.workspace_bytes, opts, stream, &work, &owned)) return st;
+      Int8Args g = make_int8_args(pl, m, n, k, A, lda, B, ldb, C, ldc, (int8_t*)work);
+      int e = launch_int8_digitize(pl.digits_a, g, stream);
+      if (!e) e = launch_int8_gemm(pl.digits_a, &g, 1, stream);
+      const int st = hip_status(e);
+      const int st2 = release_workspace(work, owned, stream);
+      return st ? st : st2;
     }
-
-    mmp::Fp64Args a;
-    std::memset(&a, 0, sizeof(a));
-    a.A = A;
-    a.B = B;
-    a.C = C;
-    a.m = m;
-    a.n = n;
-    a.k = k;
-    a.lda = lda;
-    a.ldb = ldb;
-    a.ldc = ldc;
-    a.p = (double)p;
-    a.q = pl.q;
-    a.alpha = (double)pl.alpha;
-    a.beta = (double)pl.beta;
-    a.ainv = (pl.u > 1 && is_pow2(pl.alpha)) ? 1.0 / (double)pl.alpha : 0.0;
-    a.binv = (pl.v > 1 && is_pow2(pl.beta)) ? 1.0 / (double)pl.beta : 0.0;
-    a.L = (int)pl.kblock;
-    a.S = pl.slots;
-    a.KR = (pl.slots <= mmp::kBK) ? (mmp::kBK / pl.slots) * (int)pl.kblock : mmp::kBK;
-    a.stages_per_block = pl.slots >= mmp::kBK ? pl.slots / mmp::kBK : 1;
-    a.lazy = pl.lazy;
-    return hip_status(mmp::launch_fp64_words(pl.u, pl.v, pl.tile, a, stream));
+    Fp64Batch b;
+    std::memset(&b, 0, sizeof(b));
+    b.njobs = 1;
+    b.job[0] = make_fp64_args(pl, m, n, k, A, lda, B, ldb, C, ldc);
+    return hip_status(launch_fp64_words(pl.u, pl.v, pl.tile, b, stream));
   } catch (...) {
     return MMP_EINVAL;
   }

@@ -11,14 +11,15 @@
 
 namespace mmp {
 
-int MMP_CAT(launch_fp64_words_, MMP_U, MMP_V)(int tile_id, const Fp64Args& a, void* stream) {
+int MMP_CAT(launch_fp64_words_, MMP_U, MMP_V)(int tile_id, const Fp64Batch& a, void* stream) {
   using namespace fp64w;
   static_assert(MMP_U * MMP_V <= kMaxWordProducts, "unsupported word pair");
   constexpr int UV = MMP_U * MMP_V;
   hipStream_t s = (hipStream_t)stream;
   (void)UV;
-  // k-steps per in-loop reduction: S / 4 for S in {4, 8}, else 4 (whole stages)
-  const int fe = a.S == 4 ? 1 : a.S == 8 ? 2 : 4;
+  // k-steps per in-loop reduction: S / 4 for S in {4, 8}, else 4 (whole
+  // stages); every product of a batch has the same period
+  const int fe = a.job[0].S == 4 ? 1 : a.job[0].S == 8 ? 2 : 4;
 #define MMP_SHAPE(ID_)                                                  \
   if (tile_id == ID_) {                                                 \
     if (fe == 1) return launch_shape<MMP_U, MMP_V, ID_, 1>(a, s);       \

@@ -1,4 +1,5 @@
-// One digit count D of the INT8-digit form, selected at build time by MMP_D.
+// One digit count D of the INT8-digit form, selected at build time by MMP_D:
+// the digitizing passes of one product and the digit GEMM of a batch.
 #include "int8_digits_kernel.h"
 
 #if !defined(MMP_D)
@@ -10,47 +11,144 @@
 
 namespace mmp {
 
-int MMP_CAT(launch_int8_digits_, MMP_D)(const Int8Args& g, void* stream) {
+#if MMP_D <= 7  // residues of p < 2^52 need at most 7 digits
+
+// side 0: X is A (rows x cols = m x k) -> planes [D][m][kp];
+// side 1: X is B (rows x cols = k x n) -> transposed planes [D][n][kp].
+int MMP_CAT(launch_int8_digitize_side_, MMP_D)(int side, const double* X, int64_t rows, int64_t cols, int64_t ld,
+                                               int64_t kp, uint64_t p, int8_t* out, void* stream) {
   using namespace i8d;
   constexpr int D = MMP_D;
   hipStream_t s = (hipStream_t)stream;
   // largest value D signed base-256 digits reach: 127 (256^D - 1) / 255
   int64_t top = 0;
   for (int i = 0; i < D; i++) top = top * 256 + 127;
-  const int64_t kp = g.kp;
-  int8_t* Ad = g.work;
-  int8_t* Bd = g.work + (size_t)D * g.m * kp;
-  {
-    const int64_t total = g.m * (kp / 4);
+  const ResidueIn in{X, (int64_t)p, top};
+  if (side == 0) {
+    const int64_t total = rows * (kp / 4);
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL((digitize_rows_kernel<D>), dim3((unsigned)blocks), dim3(256), 0, s, g.A, g.m, g.k,
-                       g.lda, kp, (int64_t)g.p, top, Ad);
-    if (hipError_t e = hipGetLastError()) return (int)e;
+    TimerTok* t = timer_begin("int8_digitize_a");
+    hipExtLaunchKernelGGL((digitize_rows_kernel<D, ResidueIn>), dim3((unsigned)blocks), dim3(256), 0, s,
+                          timer_start(t), timer_stop(t), 0, in, rows, cols, ld, kp, out);
+    const hipError_t e = hipGetLastError();
+    timer_commit(t, (int)e);
+    return (int)e;
   }
-  {
-    const int64_t tiles = (kp / 64) * ((g.n + 63) / 64);
-    if (tiles > 0x7fffffff) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL((digitize_cols_kernel<D>), dim3((unsigned)tiles), dim3(256), 0, s, g.B, g.k, g.n,
-                       g.ldb, kp, (int64_t)g.p, top, Bd);
-    if (hipError_t e = hipGetLastError()) return (int)e;
-  }
+  const int64_t tiles = (kp / 64) * ((cols + 63) / 64);
+  if (tiles > 0x7fffffff) return (int)hipErrorInvalidValue;
+  TimerTok* t = timer_begin("int8_digitize_b");
+  hipExtLaunchKernelGGL((digitize_cols_kernel<D, ResidueIn>), dim3((unsigned)tiles), dim3(256), 0, s,
+                        timer_start(t), timer_stop(t), 0, in, rows, cols, ld, kp, out);
+  const hipError_t e = hipGetLastError();
+  timer_commit(t, (int)e);
+  return (int)e;
+}
+
+int MMP_CAT(launch_int8_digitize_, MMP_D)(const Int8Args& g, void* stream) {
+  constexpr int D = MMP_D;
+  int8_t* Ad = g.work;
+  int8_t* Bd = g.work + (size_t)D * g.m * g.kp;
+  if (!g.resident_a)
+    if (int e = MMP_CAT(launch_int8_digitize_side_, MMP_D)(0, g.A, g.m, g.k, g.lda, g.kp, g.p, Ad, stream)) return e;
+  if (!g.resident_b)
+    if (int e = MMP_CAT(launch_int8_digitize_side_, MMP_D)(1, g.B, g.k, g.n, g.ldb, g.kp, g.p, Bd, stream)) return e;
+  return 0;
+}
+
+int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* stream) {
+  using namespace i8d;
+  constexpr int D = MMP_D;
   constexpr int TM = I8Tile<D>::tm, TN = I8Tile<D>::tn;
   constexpr int BM = 32 * TM, BN = 32 * TN;
-  const int64_t nb = ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN);
-  if (nb > 0x7fffffff) return (int)hipErrorInvalidValue;
-  GemmArgs a;
+  if (njobs < 1 || njobs > kMaxBatch) return (int)hipErrorInvalidValue;
+  GemmBatch b;
+  b.njobs = njobs;
+  int64_t total = 0;
+  for (int j = 0; j < njobs; j++) {
+    const Int8Args& g = jobs[j];
+    GemmArgs& a = b.job[j];
+    a.Ad = g.resident_a ? g.resident_a : g.work;
+    a.Bd = g.resident_b ? g.resident_b : g.work + (size_t)D * g.m * g.kp;
+    a.C = g.C;
+    a.m = g.m;
+    a.n = g.n;
+    a.kp = g.kp;
+    a.ldc = g.ldc;
+    a.p = (double)g.p;
+    a.q = g.q;
+    a.stages_per_block = g.kblock / kBK8;
+    b.tile_start[j] = (int)total;
+    total += ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN);
+    if (total > 0x7fffffff) return (int)hipErrorInvalidValue;
+  }
+  b.tile_start[njobs] = (int)total;
+  if (total <= 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  TimerTok* t = timer_begin("int8_gemm");
+  hipExtLaunchKernelGGL((int8_digits_gemm_kernel<D, TM, TN>), dim3((unsigned)total), dim3(kThreads), 0, s,
+                        timer_start(t), timer_stop(t), 0, b);
+  const int e = (int)hipGetLastError();
+  timer_commit(t, e);
+  return e;
+}
+
+#endif
+
+int MMP_CAT(launch_crt_, MMP_D)(const CrtLaunch& c, void* stream) {
+  using namespace i8d;
+  constexpr int D = MMP_D;
+  constexpr int TM = I8Tile<D>::tm, TN = I8Tile<D>::tn;
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  static_assert(kMaxPrimes == kMaxPrimesCrt, "prime table sizes");
+  hipStream_t s = (hipStream_t)stream;
+  if (c.nprimes < 1 || c.nprimes > kMaxPrimes) return (int)hipErrorInvalidValue;
+  const int64_t kp = c.kp;
+  int8_t* Ad = c.work;
+  int8_t* Bd = c.work + (size_t)D * c.m * kp;
+  {
+    const IntegerIn in{c.A};
+    const int64_t total = c.m * (kp / 4);
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    TimerTok* t = timer_begin("crt_digitize_a");
+    hipExtLaunchKernelGGL((digitize_rows_kernel<D, IntegerIn>), dim3((unsigned)blocks), dim3(256), 0, s,
+                          timer_start(t), timer_stop(t), 0, in, c.m, c.k, c.lda, kp, Ad);
+    const hipError_t e = hipGetLastError();
+    timer_commit(t, (int)e);
+    if (e) return (int)e;
+  }
+  {
+    const IntegerIn in{c.B};
+    const int64_t tiles = (kp / 64) * ((c.n + 63) / 64);
+    if (tiles > 0x7fffffff) return (int)hipErrorInvalidValue;
+    TimerTok* t = timer_begin("crt_digitize_b");
+    hipExtLaunchKernelGGL((digitize_cols_kernel<D, IntegerIn>), dim3((unsigned)tiles), dim3(256), 0, s,
+                          timer_start(t), timer_stop(t), 0, in, c.k, c.n, c.ldb, kp, Bd);
+    const hipError_t e = hipGetLastError();
+    timer_commit(t, (int)e);
+    if (e) return (int)e;
+  }
+  CrtArgs a;
   a.Ad = Ad;
   a.Bd = Bd;
-  a.C = g.C;
-  a.m = g.m;
-  a.n = g.n;
+  a.m = c.m;
+  a.n = c.n;
   a.kp = kp;
-  a.ldc = g.ldc;
-  a.p = (double)g.p;
-  a.q = g.q;
-  a.stages_per_block = g.kblock / kBK8;
-  hipLaunchKernelGGL((int8_digits_gemm_kernel<D, TM, TN>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
-  return (int)hipGetLastError();
+  a.ldc = c.ldc;
+  a.nprimes = c.nprimes;
+  for (int i = 0; i < c.nprimes; i++) {
+    a.p[i] = (double)c.p[i];
+    a.q[i] = 1.0 / (double)c.p[i];
+    a.C[i] = c.C[i];
+  }
+  const int64_t nb = ((c.m + BM - 1) / BM) * ((c.n + BN - 1) / BN);
+  if (nb <= 0) return 0;
+  if (nb > 0x7fffffff) return (int)hipErrorInvalidValue;
+  TimerTok* t = timer_begin("crt_gemm");
+  hipExtLaunchKernelGGL((crt_gemm_kernel<D, TM, TN>), dim3((unsigned)nb), dim3(kThreads), 0, s,
+                        timer_start(t), timer_stop(t), 0, a);
+  const int e = (int)hipGetLastError();
+  timer_commit(t, e);
+  return e;
 }
 
 }  // namespace mmp

@@ -4,6 +4,9 @@
 #include <cstddef>
 #include <cstdint>
 
+#include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
+
 #include "mmp.h"
 
 namespace mmp {
@@ -14,6 +17,7 @@ constexpr uint64_t kPMax = 1ull << (kT - 1);        // p < 2^(t-1)  (Alg. 1)
 constexpr int kMaxWords = 4;                        // u, v <= 4
 constexpr int kMaxWordProducts = 8;                 // u v <= 8
 constexpr int kBK = 16;                             // k-slots per LDS stage (FP64 form)
+constexpr int kMaxBatch = 16;                       // products per batched launch
 
 // FP64-form tile shapes.  A workgroup is 4 waves in a 2 x 2 grid; each wave
 // owns TM x TN MFMA tiles of 16 x 16 outputs for every word pair.
@@ -72,17 +76,90 @@ struct Int8Args {
   uint64_t p;
   double q;
   int64_t kblock;    // k-terms per int32 accumulation block (multiple of 64)
-  int8_t* work;      // D (m + n) kp bytes
+  int8_t* work;      // D (m + n) kp bytes: planes of A, then of B^T
+  const int8_t* resident_a;  // optional ready planes of A (then A is not digitised)
+  const int8_t* resident_b;  // optional ready planes of B^T
 };
+// Digit planes of one operand side into out (side 0: A rows -> [D][rows][kp];
+// side 1: B columns -> [D][cols][kp]).
+int launch_int8_digitize_side(int digits, int side, const double* X, int64_t rows, int64_t cols, int64_t ld,
+                              int64_t kp, uint64_t p, int8_t* out, void* stream);
 int digits_for(uint64_t p);                       // ceil(bitsize(p) / 8)
 int64_t int8_kblock(int digits);                  // exact-int32 block length
 size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k);
-int launch_int8_digits(int digits, const Int8Args& a, void* stream);
+// Multi-modular product of one integer pair (uint64 entries < 2^entry_bits)
+// against up to kMaxPrimesCrt moduli, all from one digit GEMM; needs
+// k <= int8_kblock(digits).
+constexpr int kMaxPrimesCrt = 64;
+struct CrtLaunch {
+  const uint64_t* A;
+  const uint64_t* B;
+  int64_t m, n, k, lda, ldb, ldc;
+  int64_t kp;
+  int nprimes;
+  uint64_t p[kMaxPrimesCrt];
+  double* C[kMaxPrimesCrt];
+  int8_t* work;  // digits (m + n) kp bytes
+};
+int crt_digits(int entry_bits);  // ceil((entry_bits + 1) / 8), signed digits of values < 2^entry_bits
+int launch_crt(int digits, const CrtLaunch& c, void* stream);
+
+// Digit planes of one product into a.work, then the digit GEMM of up to
+// kMaxBatch products with the same digit count (each with its own planes).
+int launch_int8_digitize(int digits, const Int8Args& a, void* stream);
+int launch_int8_gemm(int digits, const Int8Args* jobs, int njobs, void* stream);
+
+// Phase timer hooks (null tokens unless mmp_timers_enable(1)).  A launch
+// passes timer_start(t) / timer_stop(t) as the start and stop events of
+// hipExtLaunchKernelGGL, then hands the token back with timer_commit.
+struct TimerTok {
+  hipEvent_t e0, e1;
+  const char* name;
+};
+TimerTok* timer_begin(const char* phase);
+void timer_commit(TimerTok* t, int launch_status);
+inline hipEvent_t timer_start(TimerTok* t) { return t ? t->e0 : nullptr; }
+inline hipEvent_t timer_stop(TimerTok* t) { return t ? t->e1 : nullptr; }
+
+// Up to kMaxBatch products of one kernel configuration in one launch; the
+// job table travels in the kernel arguments (no device allocation, so a
+// launch can be captured into a graph as is).
+struct Fp64Batch {
+  int njobs;
+  int tile_start[kMaxBatch + 1];  // filled by the launcher
+  Fp64Args job[kMaxBatch];
+};
+// k-steps per in-loop reduction class of a plan: jobs of one launch share it
+inline int fp64_fe(int slots) { return slots == 4 ? 1 : slots == 8 ? 2 : 4; }
 
 // Launch the fused FP64-word kernel; returns a hipError_t value (0 = success).
-int launch_fp64_words(int u, int v, int tile_id, const Fp64Args& a, void* stream);
+int launch_fp64_words(int u, int v, int tile_id, const Fp64Batch& a, void* stream);
 // Fill a row-major m x n matrix (leading dimension ld) with +0.0.
 int launch_zero_fill(double* C, int64_t m, int64_t n, int64_t ld, void* stream);
+// Scan for uint64 entries at or above 2^bits; sets *flag nonzero.
+int launch_validate_bits(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld, int bits, int* flag,
+                         void* stream);
+// out[r][c] = X[r][c] mod p as binary64 (integer reduction on the device).
+int launch_reduce_mod(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld, uint64_t p, double* out,
+                      int64_t ldo, void* stream);
+
+// Host helpers shared by the entry points (mmp_abi.cpp).
+int hip_status(int err);
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes);
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld);
+int check_product_args(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, const double* C, int64_t ldc);
+int acquire_workspace(size_t bytes, const mmp_opts* opts, void* stream, void** out, bool* owned);
+int release_workspace(void* ptr, bool owned, void* stream);
+int validate_product_entries(uint64_t p, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, void* stream);
+int validate_integer_entries(int bits, int64_t m, int64_t n, int64_t k, const uint64_t* A, int64_t lda,
+                             const uint64_t* B, int64_t ldb, void* stream);
+Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double* C, int64_t ldc);
+Int8Args make_int8_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double* C, int64_t ldc, int8_t* work);
+
 // Scan for entries outside [0, p) or non-integral; sets *flag (device int) nonzero.
 int launch_validate(const double* X, int64_t rows, int64_t cols, int64_t ld, double p, int* flag,
                     void* stream);

@@ -8,7 +8,7 @@
 
 namespace mmp {
 
-#define MMP_DECL(U_, V_) int launch_fp64_words_##U_##_##V_(int tile_id, const Fp64Args& a, void* stream);
+#define MMP_DECL(U_, V_) int launch_fp64_words_##U_##_##V_(int tile_id, const Fp64Batch& a, void* stream);
 MMP_DECL(1, 1)
 MMP_DECL(1, 2)
 MMP_DECL(2, 1)
@@ -23,7 +23,7 @@ MMP_DECL(2, 4)
 MMP_DECL(4, 2)
 #undef MMP_DECL
 
-int launch_fp64_words(int u, int v, int tile_id, const Fp64Args& a, void* stream) {
+int launch_fp64_words(int u, int v, int tile_id, const Fp64Batch& a, void* stream) {
 #define MMP_UV(U_, V_) \
   if (u == U_ && v == V_) return launch_fp64_words_##U_##_##V_(tile_id, a, stream);
   MMP_UV(1, 1)
@@ -42,7 +42,11 @@ int launch_fp64_words(int u, int v, int tile_id, const Fp64Args& a, void* stream
   return (int)hipErrorInvalidValue;
 }
 
-#define MMP_DECL8(D_) int launch_int8_digits_##D_(const Int8Args& a, void* stream);
+#define MMP_DECL8(D_)                                                                               \
+  int launch_int8_digitize_##D_(const Int8Args& a, void* stream);                                   \
+  int launch_int8_gemm_##D_(const Int8Args* jobs, int njobs, void* stream);                         \
+  int launch_int8_digitize_side_##D_(int side, const double* X, int64_t rows, int64_t cols, int64_t ld, \
+                                     int64_t kp, uint64_t p, int8_t* out, void* stream);
 MMP_DECL8(1)
 MMP_DECL8(2)
 MMP_DECL8(3)
@@ -52,15 +56,72 @@ MMP_DECL8(6)
 MMP_DECL8(7)
 #undef MMP_DECL8
 
-int launch_int8_digits(int digits, const Int8Args& a, void* stream) {
+#define MMP_DECLC(D_) int launch_crt_##D_(const CrtLaunch& c, void* stream);
+MMP_DECLC(1)
+MMP_DECLC(2)
+MMP_DECLC(3)
+MMP_DECLC(4)
+MMP_DECLC(5)
+MMP_DECLC(6)
+MMP_DECLC(7)
+MMP_DECLC(8)
+#undef MMP_DECLC
+
+int crt_digits(int entry_bits) { return (entry_bits + 1 + 7) / 8; }
+
+int launch_crt(int digits, const CrtLaunch& c, void* stream) {
   switch (digits) {
-    case 1: return launch_int8_digits_1(a, stream);
-    case 2: return launch_int8_digits_2(a, stream);
-    case 3: return launch_int8_digits_3(a, stream);
-    case 4: return launch_int8_digits_4(a, stream);
-    case 5: return launch_int8_digits_5(a, stream);
-    case 6: return launch_int8_digits_6(a, stream);
-    case 7: return launch_int8_digits_7(a, stream);
+    case 1: return launch_crt_1(c, stream);
+    case 2: return launch_crt_2(c, stream);
+    case 3: return launch_crt_3(c, stream);
+    case 4: return launch_crt_4(c, stream);
+    case 5: return launch_crt_5(c, stream);
+    case 6: return launch_crt_6(c, stream);
+    case 7: return launch_crt_7(c, stream);
+    case 8: return launch_crt_8(c, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+int launch_int8_digitize(int digits, const Int8Args& a, void* stream) {
+  switch (digits) {
+    case 1: return launch_int8_digitize_1(a, stream);
+    case 2: return launch_int8_digitize_2(a, stream);
+    case 3: return launch_int8_digitize_3(a, stream);
+    case 4: return launch_int8_digitize_4(a, stream);
+    case 5: return launch_int8_digitize_5(a, stream);
+    case 6: return launch_int8_digitize_6(a, stream);
+    case 7: return launch_int8_digitize_7(a, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+int launch_int8_digitize_side(int digits, int side, const double* X, int64_t rows, int64_t cols, int64_t ld,
+                              int64_t kp, uint64_t p, int8_t* out, void* stream) {
+#define MMP_SIDE(D_) \
+  case D_: return launch_int8_digitize_side_##D_(side, X, rows, cols, ld, kp, p, out, stream);
+  switch (digits) {
+    MMP_SIDE(1)
+    MMP_SIDE(2)
+    MMP_SIDE(3)
+    MMP_SIDE(4)
+    MMP_SIDE(5)
+    MMP_SIDE(6)
+    MMP_SIDE(7)
+    default: return (int)hipErrorInvalidValue;
+  }
+#undef MMP_SIDE
+}
+
+int launch_int8_gemm(int digits, const Int8Args* jobs, int njobs, void* stream) {
+  switch (digits) {
+    case 1: return launch_int8_gemm_1(jobs, njobs, stream);
+    case 2: return launch_int8_gemm_2(jobs, njobs, stream);
+    case 3: return launch_int8_gemm_3(jobs, njobs, stream);
+    case 4: return launch_int8_gemm_4(jobs, njobs, stream);
+    case 5: return launch_int8_gemm_5(jobs, njobs, stream);
+    case 6: return launch_int8_gemm_6(jobs, njobs, stream);
+    case 7: return launch_int8_gemm_7(jobs, njobs, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
@@ -89,7 +150,49 @@ __global__ void validate_kernel(const double* X, int64_t rows, int64_t cols, int
   if (bad) atomicOr(flag, 1);
 }
 
+__global__ void validate_bits_kernel(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld, int bits,
+                                     int* flag) {
+  const int64_t total = rows * cols;
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i - (i / cols) * cols;
+    if ((X[r * ld + c] >> bits) != 0) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void reduce_mod_kernel(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld, uint64_t p,
+                                  double* out, int64_t ldo) {
+  const int64_t total = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i - (i / cols) * cols;
+    out[r * ldo + c] = (double)(X[r * ld + c] % p);
+  }
+}
+
 }  // namespace
+
+int launch_validate_bits(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld, int bits, int* flag,
+                         void* stream) {
+  if (rows <= 0 || cols <= 0) return 0;
+  const int64_t total = rows * cols;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(validate_bits_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, X, rows,
+                     cols, ld, bits, flag);
+  return (int)hipGetLastError();
+}
+
+int launch_reduce_mod(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld, uint64_t p, double* out,
+                      int64_t ldo, void* stream) {
+  if (rows <= 0 || cols <= 0) return 0;
+  const int64_t total = rows * cols;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(reduce_mod_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, X, rows,
+                     cols, ld, p, out, ldo);
+  return (int)hipGetLastError();
+}
 
 int launch_zero_fill(double* C, int64_t m, int64_t n, int64_t ld, void* stream) {
   if (m <= 0 || n <= 0) return 0;

@@ -100,3 +100,22 @@ def test_sweep_shapes(idx):
     say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
     A, B, C = _compute(prob)
     _check_sampled(prob, A, B, C, nrows=1, ncols=1, nrand=512)
+
+
+def test_crt_2048_32_primes():
+    job = gen.crt_job()
+    A, B = job.a(), job.b()
+    dA = torch.from_numpy(A.astype(np.int64)).cuda()
+    dB = torch.from_numpy(B.astype(np.int64)).cuda()
+    outs = [torch.full((job.m, job.n), -1.0, dtype=torch.float64, device="cuda") for _ in job.primes]
+    say("crt config", job.m, job.n, job.k, len(job.primes), [p.bit_length() for p in job.primes])
+    mmp.mm_modp_crt(dA, dB, job.primes, outs, job.bits)
+    torch.cuda.synchronize()
+    rng = gen.uniform_mod(job.seed, 78, 2 * 256, 1 << 40)
+    rr = np.array([int(x) % job.m for x in rng[:256]] + [0, job.m - 1], dtype=np.int64)
+    cc = np.array([int(x) % job.n for x in rng[256:]] + [job.n - 1, 0], dtype=np.int64)
+    for p, C in zip(job.primes, outs):
+        assert bool(torch.all((C >= 0) & (C < p) & (C == torch.floor(C))))
+        want = oracle.mm_modp_entries(p, A, B, rr, cc).astype(np.float64)
+        got = C[torch.from_numpy(rr).cuda(), torch.from_numpy(cc).cuda()].cpu().numpy()
+        assert np.array_equal(got, want), p
