@@ -28,9 +28,7 @@ namespace i8d {
 
 typedef int int4v __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;  // 4 waves, 2 x 2
-constexpr int kBK8 = 64;       // k-bytes per LDS stage (one 16x16x64 MFMA deep)
-constexpr int kRow = kBK8 + 16; // LDS row stride in bytes: 16 lanes' 16-byte reads hit disjoint banks
+constexpr int kBK8 = 64;  // k-terms (bytes) per LDS stage: one 16x16x64 MFMA deep
 
 __device__ __forceinline__ double fmod_full(double x, double p, double q) {
   const double c = floor(x * q);
@@ -175,92 +173,130 @@ struct GemmBatch {
   GemmArgs job[kMaxBatch];
 };
 
-// LDS planes of one stage: D digit planes of a BM x 64 slab of A and of a
-// BN x 64 slab of B^T, rows padded to kRow bytes.
-template <int D, int BM, int BN>
-struct DigitStage {
-  int8_t A[D][BM][kRow];
-  int8_t B[D][BN][kRow];
+// Workgroup shape per digit count.  WM x WN waves, each owning TM x TN
+// 16x16 output tiles for all 2D - 1 digit weights; accumulator VGPRs per lane
+// = (2D - 1) TM TN 4.  Two waves per SIMD hide the LDS and load latency, so
+// every shape keeps a wave within 256 VGPRs: 4-wave groups (two groups per
+// CU) up to 5 digits, one 8-wave group with narrower wave tiles beyond.
+template <int D>
+struct I8Shape {
+  static constexpr int WM = 2;
+  static constexpr int WN = D <= 5 ? 2 : 4;
+  static constexpr int TM = 2;
+  static constexpr int TN = D <= 5 ? 2 : 1;
+  static constexpr int BM = WM * TM * 16;  // 64
+  static constexpr int BN = WN * TN * 16;  // 64
+  static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int GROUPS_PER_CU = D <= 5 ? 2 : 1;
 };
 
-// The digit-product loop of one BM x BN tile: for every LDS stage of 64
-// k-terms, all D^2 digit products on 16x16x64 INT8 MFMAs into the 2D - 1
-// digit-weight accumulators; fold() runs after every stages_per_block stages
-// and once at the end if the last block is partial.
-template <int D, int TM, int TN, class Fold>
+// Ring of two LDS stages; each holds D digit planes of a BM x 64 slab of A
+// and of a BN x 64 slab of B^T, 64 bytes per row with no padding.  The four
+// 16-byte chunks of row r are stored in the order q ^ ((r >> 2) & 3), so the
+// 16 rows that one MFMA operand read touches fall in 16 distinct bank groups.
+constexpr int kStages = 2;
+template <int D, int BM, int BN>
+struct DigitRing {
+  int8_t s[kStages][D][BM + BN][64];
+};
+
+__device__ __forceinline__ int swz(int r, int q) { return ((q ^ (r >> 2)) & 3) * 16; }
+
+// wait until at most N vector-memory operations of this wave are outstanding
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// The digit-product loop of one BM x BN tile.  Stage st + 1's slabs are
+// copied from HBM straight into LDS (global_load_lds, 1 KB per wave
+// instruction) while stage st is multiplied: all D^2 digit products on
+// 16x16x64 INT8 MFMAs into the 2D - 1 digit-weight accumulators.  fold()
+// runs after every stages_per_block stages and once at the end if the last
+// block is partial.  Rows and columns past the matrix edge read an in-range
+// row instead (their outputs are never stored); the k tail is zero in the
+// planes.
+template <int D, class S, class Fold>
 __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, const int8_t* __restrict__ Bd,
                                                 int64_t m, int64_t n, int64_t kp, int64_t m0, int64_t n0,
-                                                int64_t stages_per_block,
-                                                DigitStage<D, 32 * TM, 32 * TN>& sm,
-                                                int4v (&acc)[2 * D - 1][TM][TN], Fold fold) {
-  constexpr int BM = 32 * TM;
-  constexpr int BN = 32 * TN;
-  constexpr int CHUNKS_A = D * BM * (kBK8 / 16);  // 16-byte chunks per stage
-  constexpr int CHUNKS_B = D * BN * (kBK8 / 16);
-  constexpr int NCA = (CHUNKS_A + kThreads - 1) / kThreads;
-  constexpr int NCB = (CHUNKS_B + kThreads - 1) / kThreads;
+                                                int64_t stages_per_block, DigitRing<D, S::BM, S::BN>& sm,
+                                                int4v (&acc)[2 * D - 1][S::TM][S::TN], Fold fold) {
+  constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
+  constexpr int NW = S::WM * S::WN;
+  constexpr int GROUPS = D * (BM + BN) / 16;  // 1 KB copy instructions per stage
+  static_assert(GROUPS % NW == 0, "whole copy instructions per wave");
+  constexpr int IPW = GROUPS / NW;
+  static_assert(IPW < 64, "vmcnt range");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * TM * 16, wn = (wave & 1) * TN * 16;
+  const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int64_t planeA = m * kp, planeB = n * kp;
+  const int rl = lane >> 2;                       // row within a 16-row group
+  const int ql = (lane & 3) ^ ((lane >> 4) & 3);  // chunk this lane copies
 
-  int4v pa[NCA], pb[NCB];
-  auto load_stage = [&](int64_t k0) {
+  const int8_t* src[IPW];
+  int dst_plane[IPW], dst_row[IPW];
 #pragma unroll
-    for (int e = 0; e < NCA; e++) {
-      const int c = tid + e * kThreads;
-      const int i = c / (BM * 4), rem = c % (BM * 4), r = rem / 4, q = rem % 4;
-      const int64_t row = m0 + r;
-      pa[e] = (c < CHUNKS_A && row < m) ? *(const int4v*)(Ad + i * planeA + row * kp + k0 + 16 * q)
-                                       : (int4v){0, 0, 0, 0};
+  for (int e = 0; e < IPW; e++) {
+    const int t = wave + NW * e;
+    if (t < D * BM / 16) {
+      const int i = t / (BM / 16), g = t % (BM / 16);
+      int64_t row = m0 + 16 * g + rl;
+      row = row < m ? row : m - 1;
+      src[e] = Ad + i * planeA + row * kp + 16 * ql;
+      dst_plane[e] = i;
+      dst_row[e] = 16 * g;
+    } else {
+      const int t2 = t - D * BM / 16;
+      const int i = t2 / (BN / 16), g = t2 % (BN / 16);
+      int64_t col = n0 + 16 * g + rl;
+      col = col < n ? col : n - 1;
+      src[e] = Bd + i * planeB + col * kp + 16 * ql;
+      dst_plane[e] = i;
+      dst_row[e] = BM + 16 * g;
     }
+  }
+  const int64_t nstages = kp / 64;
+  auto issue = [&](int64_t st) {
+    const int b = (int)(st & 1);
 #pragma unroll
-    for (int e = 0; e < NCB; e++) {
-      const int c = tid + e * kThreads;
-      const int i = c / (BN * 4), rem = c % (BN * 4), r = rem / 4, q = rem % 4;
-      const int64_t col = n0 + r;
-      pb[e] = (c < CHUNKS_B && col < n) ? *(const int4v*)(Bd + i * planeB + col * kp + k0 + 16 * q)
-                                       : (int4v){0, 0, 0, 0};
-    }
-  };
-  auto store_stage = [&]() {
-#pragma unroll
-    for (int e = 0; e < NCA; e++) {
-      const int c = tid + e * kThreads;
-      if (c < CHUNKS_A) {
-        const int i = c / (BM * 4), rem = c % (BM * 4), r = rem / 4, q = rem % 4;
-        *(int4v*)(&sm.A[i][r][16 * q]) = pa[e];
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < NCB; e++) {
-      const int c = tid + e * kThreads;
-      if (c < CHUNKS_B) {
-        const int i = c / (BN * 4), rem = c % (BN * 4), r = rem / 4, q = rem % 4;
-        *(int4v*)(&sm.B[i][r][16 * q]) = pb[e];
-      }
-    }
+    for (int e = 0; e < IPW; e++)
+      __builtin_amdgcn_global_load_lds((const void*)(src[e] + st * 64),
+                                       (__attribute__((address_space(3))) void*)&sm.s[b][dst_plane[e]][dst_row[e]][0],
+                                       16, 0, 0);
   };
 
-  const int64_t nstages = kp / kBK8;
-  const int lrow = lane & 15, lk = (lane >> 4) * 16;
+  const int lrow = lane & 15, lq = lane >> 4;
+  if (nstages > 0) issue(0);
   int64_t in_block = 0;
-  if (nstages > 0) load_stage(0);
   for (int64_t st = 0; st < nstages; st++) {
-    __syncthreads();
-    store_stage();
-    __syncthreads();
-    if (st + 1 < nstages) load_stage((st + 1) * kBK8);
-
+    // This wave's copies of stage st are complete; the barrier extends that
+    // to every wave and ends the reads of stage st - 1, whose buffer the
+    // next copies overwrite.  A bare barrier: a fence here would also wait
+    // for copies that may still be in flight; the empty asm statements keep
+    // the compiler from moving LDS accesses or copies across it.
+    wait_vm<0>();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (st + 1 < nstages) issue(st + 1);
+    const int b = (int)(st & 1);
     int4v bf[D][TN];
 #pragma unroll
     for (int j = 0; j < D; j++)
 #pragma unroll
-      for (int y = 0; y < TN; y++) bf[j][y] = *(const int4v*)(&sm.B[j][wn + y * 16 + lrow][lk]);
+      for (int y = 0; y < TN; y++) {
+        const int r = BM + wn + y * 16 + lrow;
+        bf[j][y] = *(const int4v*)(&sm.s[b][j][r][swz(r, lq)]);
+      }
 #pragma unroll
     for (int i = 0; i < D; i++) {
       int4v af[TM];
 #pragma unroll
-      for (int x = 0; x < TM; x++) af[x] = *(const int4v*)(&sm.A[i][wm + x * 16 + lrow][lk]);
+      for (int x = 0; x < TM; x++) {
+        const int r = wm + x * 16 + lrow;
+        af[x] = *(const int4v*)(&sm.s[b][i][r][swz(r, lq)]);
+      }
 #pragma unroll
       for (int j = 0; j < D; j++)
 #pragma unroll
@@ -277,19 +313,20 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
   if (in_block != 0) fold();
 }
 
-template <int D, int TM, int TN>
-__global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmBatch bt) {
+template <int D>
+__global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) void int8_digits_gemm_kernel(
+    const GemmBatch bt) {
+  using S = I8Shape<D>;
   constexpr int ND = 2 * D - 1;
-  constexpr int BM = 32 * TM;
-  constexpr int BN = 32 * TN;
-  __shared__ __attribute__((aligned(16))) DigitStage<D, BM, BN> sm;
+  constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
+  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN> sm;
 
   int job = 0;
   while (job + 1 < bt.njobs && (int)blockIdx.x >= bt.tile_start[job + 1]) job++;
   const GemmArgs& a = bt.job[job];
   const int local_bid = (int)blockIdx.x - bt.tile_start[job];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * TM * 16, wn = (wave & 1) * TN * 16;
+  const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
   int tmi, tni;
   tile_coords(local_bid, nbm * nbn, nbm, nbn, tmi, tni);
@@ -334,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void int8_digits_gemm_kernel(const GemmBa
 #pragma unroll
         for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
   };
-  digit_tile_loop<D, TM, TN>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.stages_per_block, sm, acc, fold);
+  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.stages_per_block, sm, acc, fold);
 
   // 16x16x64 INT8 MFMA output layout: D[i][j] is value (i & 3) of lane j + 16 (i >> 2).
   const int lrow = lane & 15;
@@ -366,14 +403,15 @@ struct CrtArgs {
   double* C[kMaxPrimes];
 };
 
-template <int D, int TM, int TN>
-__global__ __launch_bounds__(kThreads) void crt_gemm_kernel(const CrtArgs a) {
+template <int D>
+__global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) void crt_gemm_kernel(
+    const CrtArgs a) {
+  using S = I8Shape<D>;
   constexpr int ND = 2 * D - 1;
-  constexpr int BM = 32 * TM;
-  constexpr int BN = 32 * TN;
-  __shared__ __attribute__((aligned(16))) DigitStage<D, BM, BN> sm;
+  constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
+  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN> sm;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * TM * 16, wn = (wave & 1) * TN * 16;
+  const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
   int tmi, tni;
   tile_coords(blockIdx.x, nbm * nbn, nbm, nbn, tmi, tni);
@@ -387,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void crt_gemm_kernel(const CrtArgs a) {
 #pragma unroll
       for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
   // one int32 block covers the whole k (checked by the launcher)
-  digit_tile_loop<D, TM, TN>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.kp / kBK8 + 1, sm, acc, [] {});
+  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.kp / kBK8 + 1, sm, acc, [] {});
 
   const int lrow = lane & 15;
   for (int pi = 0; pi < a.nprimes; pi++) {
@@ -412,13 +450,6 @@ __global__ __launch_bounds__(kThreads) void crt_gemm_kernel(const CrtArgs a) {
       }
   }
 }
-
-// Tile shape per digit count: accumulator VGPRs = (2D - 1) * TM * TN * 4.
-template <int D>
-struct I8Tile {
-  static constexpr int tm = D <= 2 ? 4 : 2;
-  static constexpr int tn = D <= 2 ? 4 : D <= 4 ? 4 : 2;
-};
 
 }  // namespace i8d
 }  // namespace mmp

@@ -58,8 +58,7 @@ int MMP_CAT(launch_int8_digitize_, MMP_D)(const Int8Args& g, void* stream) {
 int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* stream) {
   using namespace i8d;
   constexpr int D = MMP_D;
-  constexpr int TM = I8Tile<D>::tm, TN = I8Tile<D>::tn;
-  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int BM = I8Shape<D>::BM, BN = I8Shape<D>::BN;
   if (njobs < 1 || njobs > kMaxBatch) return (int)hipErrorInvalidValue;
   GemmBatch b;
   b.njobs = njobs;
@@ -85,7 +84,7 @@ int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* str
   if (total <= 0) return 0;
   hipStream_t s = (hipStream_t)stream;
   TimerTok* t = timer_begin("int8_gemm");
-  hipExtLaunchKernelGGL((int8_digits_gemm_kernel<D, TM, TN>), dim3((unsigned)total), dim3(kThreads), 0, s,
+  hipExtLaunchKernelGGL((int8_digits_gemm_kernel<D>), dim3((unsigned)total), dim3(I8Shape<D>::THREADS), 0, s,
                         timer_start(t), timer_stop(t), 0, b);
   const int e = (int)hipGetLastError();
   timer_commit(t, e);
@@ -97,8 +96,7 @@ int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* str
 int MMP_CAT(launch_crt_, MMP_D)(const CrtLaunch& c, void* stream) {
   using namespace i8d;
   constexpr int D = MMP_D;
-  constexpr int TM = I8Tile<D>::tm, TN = I8Tile<D>::tn;
-  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int BM = I8Shape<D>::BM, BN = I8Shape<D>::BN;
   static_assert(kMaxPrimes == kMaxPrimesCrt, "prime table sizes");
   hipStream_t s = (hipStream_t)stream;
   if (c.nprimes < 1 || c.nprimes > kMaxPrimes) return (int)hipErrorInvalidValue;
@@ -144,7 +142,7 @@ int MMP_CAT(launch_crt_, MMP_D)(const CrtLaunch& c, void* stream) {
   if (nb <= 0) return 0;
   if (nb > 0x7fffffff) return (int)hipErrorInvalidValue;
   TimerTok* t = timer_begin("crt_gemm");
-  hipExtLaunchKernelGGL((crt_gemm_kernel<D, TM, TN>), dim3((unsigned)nb), dim3(kThreads), 0, s,
+  hipExtLaunchKernelGGL((crt_gemm_kernel<D>), dim3((unsigned)nb), dim3(I8Shape<D>::THREADS), 0, s,
                         timer_start(t), timer_stop(t), 0, a);
   const int e = (int)hipGetLastError();
   timer_commit(t, e);
