@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="index inside the workload group")
     ap.add_argument("--form", type=int, default=0, help="0 auto, 1 FP64 words, 2 INT8 digits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extended", action="store_true",
+                    help="FP64 form: allow the extended (signed-range) block bound")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the product, time a plain device copy of this many bytes "
                          "(the reference kernel for scaling HBM counters)")
@@ -125,7 +127,7 @@ def main():
     prob = gen.config_problems(args.config)[args.variant]
     if args.form == 2:  # the INT8-digit form takes no word counts
         prob.u = prob.v = 0
-    plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, form=args.form)
+    plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, form=args.form, extended_block=args.extended)
     log("workload", prob.tag, "plan", plan)
 
     A = prob.a()
@@ -136,7 +138,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        mmp.mm_modp_async(dA, dB, dC, prob.p, prob.u, prob.v, stream=stream, form=args.form)
+        mmp.mm_modp_async(dA, dB, dC, prob.p, prob.u, prob.v, stream=stream, form=args.form,
+                          extended_block=args.extended)
 
     for _ in range(args.warmup):
         step()
@@ -219,7 +222,7 @@ def main():
                         f"2^{prob.p.bit_length()}), exact C = AB mod p",
             "m": prob.m, "n": prob.n, "k": prob.k, "p": prob.p, "bits": prob.p.bit_length(),
             "u": plan["u"], "v": plan["v"], "lambda": plan["lambda"], "kblock": plan["kblock"],
-            "digits": plan["digits_a"],
+            "digits": plan["digits_a"], "extended_block": bool(plan["extended"]),
             "form": "fp64_words" if plan["form"] == 1 else "int8_digits", "tile": plan["tile"],
         },
         "roofline": roofline,

@@ -86,7 +86,15 @@ typedef struct {
                              least the queried size) to capture a call into a
                              HIP graph. */
   size_t workspace_bytes; /* size of workspace */
-  int reserved[4];        /* must be zero */
+  int extended_block;     /* FP64 form, 1: accumulate over the whole signed
+                             exact range [-2^t, 2^t] instead of [0, 2^t]: each
+                             in-loop reduction maps the accumulator to
+                             [-2^t, -2^t + 4p) (a biased Alg. 1 with the same
+                             three operations), so a block may hold L terms
+                             with L w + 4p - 1 <= 2^(t+1), about twice the
+                             paper's lambda (project-derived bound; w is the
+                             paper's per-term bound).  0: the paper's bound. */
+  int reserved[3];        /* must be zero */
 } mmp_opts;
 
 /* What the planner decided for one product (mmp_plan fills it). */
@@ -101,7 +109,9 @@ typedef struct {
   int slots;              /* MFMA k-slots that hold one k-block (>= kblock;
                              the excess slots hold zeros) */
   int lazy;               /* 1: in-loop reductions omit Alg. 1's corrections
-                             (result in [-p, 2p)); the final one is complete */
+                             (result in [-p, 2p), or [-2^t, -2^t + 4p) with
+                             extended); the final one is complete */
+  int extended;           /* 1: the extended block bound (mmp_opts) is used */
   int tile;               /* kernel tile id */
   int bm, bn, bk;         /* workgroup tile (rows, cols, k-slots per stage) */
   int digits_a, digits_b; /* INT8 form: signed base-256 digits per operand */

@@ -35,12 +35,14 @@ STATUS = {0: "MMP_OK", -1: "MMP_EINVAL", -2: "MMP_EBOUND", -3: "MMP_ERANGE", -4:
 
 class MmpOpts(ctypes.Structure):
     _fields_ = [("form", _int), ("validate_entries", _int), ("tile", _int), ("strict_fmod", _int),
-                ("force_kblock", _i64), ("workspace", _vp), ("workspace_bytes", _sz), ("reserved", _int * 4)]
+                ("force_kblock", _i64), ("workspace", _vp), ("workspace_bytes", _sz), ("extended_block", _int),
+                ("reserved", _int * 3)]
 
 
 class MmpPlan(ctypes.Structure):
     _fields_ = [("p", _u64), ("u", _int), ("v", _int), ("form", _int), ("alpha", _u64), ("beta", _u64),
-                ("lambda_", _i64), ("kblock", _i64), ("slots", _int), ("lazy", _int), ("tile", _int),
+                ("lambda_", _i64), ("kblock", _i64), ("slots", _int), ("lazy", _int), ("extended", _int),
+                ("tile", _int),
                 ("bm", _int), ("bn", _int), ("bk", _int), ("digits_a", _int), ("digits_b", _int),
                 ("kblock_int8", _i64), ("q", _dbl), ("est_seconds", _dbl), ("workspace_bytes", _sz)]
 
@@ -129,8 +131,9 @@ def strerror(status: int) -> str:
 
 
 def _opts(form=FORM_AUTO, force_kblock=0, validate_entries=False, tile=0, strict_fmod=False,
-          workspace=None):
+          workspace=None, extended_block=False):
     o = MmpOpts()
+    o.extended_block = 1 if extended_block else 0
     o.form = form
     o.force_kblock = force_kblock
     o.validate_entries = 1 if validate_entries else 0

@@ -36,11 +36,15 @@ constexpr int kPadB = 16;      // B plane rows: BN + 16 doubles (adjacent k-slot
 
 // ---- scalar modular arithmetic (binary64, explicit fma, no reassociation)
 
-// Alg. 1 without its two corrections: d = x - floor(x q) p lies in [-p, 2p)
-// (the quotient estimate is within one of floor(x / p), Prop.
-// fpModularReductionFMA's proof), for x in [-p, 2^t].
-__device__ __forceinline__ double fmod_lazy(double x, double p, double q) {
-  const double c = floor(x * q);
+// Alg. 1 without its two corrections, optionally biased by K p:
+// c = floor(fl(x q + K)) is within one of floor(x / p) + K (the quotient
+// estimate of Prop. fpModularReductionFMA's proof, with the error of one
+// more rounding of a value below 2^(t+1) / p), so d = x - c p lies in
+// [-K p - p, -K p + 2p) for any integer |x| <= 2^t.  K = 0 gives [-p, 2p);
+// K = floor(2^t / p) - 1 gives [-2^t, -2^t + 4p), the bottom of the exact
+// range.  fma(x, q, 0) is the plain product x q.
+__device__ __forceinline__ double fmod_lazy(double x, double p, double q, double bias) {
+  const double c = floor(fma(x, q, bias));
   return fma(-c, p, x);
 }
 
@@ -202,9 +206,9 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
 #pragma unroll
       for (int x = 0; x < TM; x++)
 #pragma unroll
-        for (int y = 0; y < TN; y++) acc[i][j][x][y] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < TN; y++) acc[i][j][x][y] = (d4){a.acc_init, a.acc_init, a.acc_init, a.acc_init};
 
-  const double p = a.p, q = a.q;
+  const double p = a.p, q = a.q, bias = a.bias;
   const int64_t nstages = (a.k + KR - 1) / KR;
   const int lrow = lane & 15, lk = lane >> 4;
 
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
 #pragma unroll
           for (int y = 0; y < TN; y++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) acc[i][j][x][y][r] = fmod_lazy(acc[i][j][x][y][r], p, q);
+            for (int r = 0; r < 4; r++) acc[i][j][x][y][r] = fmod_lazy(acc[i][j][x][y][r], p, q, bias);
     if (!a.lazy) {
 #pragma unroll
       for (int i = 0; i < U; i++)

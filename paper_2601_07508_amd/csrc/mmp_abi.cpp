@@ -166,6 +166,11 @@ Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, c
   a.KR = (pl.slots <= kBK) ? (kBK / pl.slots) * (int)pl.kblock : kBK;
   a.stages_per_block = pl.slots >= kBK ? pl.slots / kBK : 1;
   a.lazy = pl.lazy;
+  if (pl.extended) {
+    const uint64_t K = (kTwoT / pl.p) - 1;  // K p <= 2^t - p
+    a.bias = (double)K;
+    a.acc_init = -(double)(K * pl.p);
+  }
   return a;
 }
 

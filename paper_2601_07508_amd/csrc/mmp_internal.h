@@ -47,6 +47,10 @@ int64_t paper_lambda(uint64_t p, int u, int v);  // eq. lambda-sw / eq. cAcB, 0 
 // correction-free reduction leaves) and stay within 2^t.
 bool lazy_block_ok(uint64_t p, int u, int v, int64_t L);
 bool supported_words(int u, int v);
+// The extended bound: a block started in [-2^t, -2^t + 4p) (the biased
+// reduction's range) stays within [-2^t, 2^t].
+bool extended_block_ok(uint64_t p, int u, int v, int64_t L);
+int64_t extended_lambda(uint64_t p, int u, int v);
 
 int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
          mmp_plan_t* out);
@@ -63,6 +67,8 @@ struct Fp64Args {
   int KR;          // real k-terms per LDS stage
   int stages_per_block;  // S >= 16: LDS stages per block (S / 16)
   int lazy;              // in-loop reductions without corrections
+  double bias;           // K in the in-loop reduction c = floor(x q + K) (0, or floor(2^t / p) - 1)
+  double acc_init;       // accumulator start value: -K p (congruent to 0)
 };
 
 // INT8-digit form: digit planes in a device workspace, then the digit GEMM.

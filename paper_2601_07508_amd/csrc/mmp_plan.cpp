@@ -53,6 +53,23 @@ int64_t paper_lambda(uint64_t p, int u, int v) {
   return (int64_t)lam;
 }
 
+bool extended_block_ok(uint64_t p, int u, int v, int64_t L) {
+  // The biased reduction leaves [-2^t, -2^t + 4p); L non-negative terms of
+  // at most w keep every partial sum within [-2^t, 2^t] if
+  // L w + 4p - 1 <= 2^(t+1).
+  u128 w = word_product_bound(p, u, v);
+  return (u128)L * w + 4 * (u128)p - 1 <= 2 * (u128)kTwoT;
+}
+
+int64_t extended_lambda(uint64_t p, int u, int v) {
+  if (p < 5 || p >= kPMax) return 0;
+  u128 w = word_product_bound(p, u, v);
+  u128 room = 2 * (u128)kTwoT - 4 * (u128)p + 1;
+  u128 lam = room / w;
+  if (lam > (u128)INT64_MAX) lam = INT64_MAX;
+  return (int64_t)lam;
+}
+
 bool lazy_block_ok(uint64_t p, int u, int v, int64_t L) {
   // A block starts from a value in [-p, 2p - 1] and adds L non-negative
   // terms, each at most w: every partial sum stays in [-p, 2^t] if
@@ -78,26 +95,37 @@ struct KBlock {
   int64_t L;
   int S;
   bool lazy;
+  bool extended;
   double cost;
 };
 
-KBlock choose_kblock(uint64_t p, int u, int v, int64_t lambda, int64_t k, bool strict) {
-  KBlock best{0, 0, false, 1e300};
-  auto consider = [&](int S, int64_t L) {
-    if (L < 1 || L > lambda) return;
-    bool lazy = !strict && lazy_block_ok(p, u, v, L);
+// Best (L, S) for one word pair.  Paper mode: L <= the paper's lambda, the
+// correction-free reduction where lazy_block_ok allows it.  With extended
+// allowed, blocks under the extended bound compete too (biased reduction);
+// near p = 2^(t-1) that bound is the smaller one and the paper mode wins.
+KBlock choose_kblock(uint64_t p, int u, int v, int64_t k, bool strict, bool allow_extended) {
+  KBlock best{0, 0, false, false, 1e300};
+  const int64_t lam_paper = paper_lambda(p, u, v);
+  const int64_t lam_ext = allow_extended ? extended_lambda(p, u, v) : 0;
+  auto consider = [&](int S, int64_t L, bool ext) {
+    if (L < 1 || L > (ext ? lam_ext : lam_paper)) return;
+    const bool lazy = ext || (!strict && lazy_block_ok(p, u, v, L));
     double c = block_cost(S, L, lazy);
     // a block longer than k never reduces in the loop: cost of the MFMAs only
     if (L >= k && k > 0) c = 64.0 * (S / 4) / (double)L;
-    if (c < best.cost - 1e-12) best = {L, S, lazy, c};
+    if (c < best.cost - 1e-12) best = {L, S, lazy, ext, c};
   };
-  for (int S : {4, 8, 16}) consider(S, lambda < S ? lambda : S);
-  // multi-stage blocks (no zero slots): L = S = 16 j
-  int64_t jmax = lambda / kBK;
-  if (jmax >= 2) {
-    int64_t cap = (int64_t)1 << 26;  // beyond this the in-loop cost is nil
-    int64_t j = jmax * kBK > cap ? cap / kBK : jmax;
-    consider((int)std::min<int64_t>(j * kBK, cap), j * kBK);
+  for (int e = 0; e < (allow_extended ? 2 : 1); e++) {
+    const bool ext = e == 1;
+    const int64_t lambda = ext ? lam_ext : lam_paper;
+    for (int S : {4, 8, 16}) consider(S, lambda < S ? lambda : S, ext);
+    // multi-stage blocks (no zero slots): L = S = 16 j
+    const int64_t jmax = lambda / kBK;
+    if (jmax >= 2) {
+      const int64_t cap = (int64_t)1 << 26;  // beyond this the in-loop cost is nil
+      const int64_t j = jmax * kBK > cap ? cap / kBK : jmax;
+      consider((int)std::min<int64_t>(j * kBK, cap), j * kBK, ext);
+    }
   }
   return best;
 }
@@ -171,6 +199,9 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
   if (o.force_kblock < 0 || o.tile < 0 || o.tile > 3) return MMP_EINVAL;
 
   const bool strict = o.strict_fmod != 0;
+  const bool extended = o.extended_block != 0;
+  if (extended && strict) return MMP_EINVAL;  // the extended range needs the biased reduction
+  if (extended && o.form == MMP_FORM_INT8_WORDS) return MMP_EINVAL;
 
   // INT8-digit form: asked for, or chosen by cost when neither the words
   // nor the block are forced.
@@ -215,9 +246,8 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
       int cu = c[0], cv = c[1];
       if (n < m && cu > cv) continue;  // words on B when B is the narrower side
       if (n > m && cv > cu) continue;
-      int64_t lam = paper_lambda(p, cu, cv);
-      if (lam < 1) continue;
-      KBlock kb = choose_kblock(p, cu, cv, lam, k, strict);
+      if (paper_lambda(p, cu, cv) < 1) continue;
+      KBlock kb = choose_kblock(p, cu, cv, k, strict, extended);
       double cost = kb.cost * cu * cv;
       if (cost < best * (1 - 1e-9)) {
         best = cost;
@@ -232,7 +262,9 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
   if (lambda < 1) return MMP_EBOUND;
   if (o.force_kblock > 0) {
     int64_t L = o.force_kblock;
-    if (L > lambda) return MMP_EBOUND;
+    // a forced block takes the paper's bound when it fits, else the extended one
+    const bool ext = L > lambda;
+    if (ext && (!extended || L > extended_lambda(p, bu, bv))) return MMP_EBOUND;
     int S;
     if (L <= 4) S = 4;
     else if (L <= 8) S = 8;
@@ -240,9 +272,9 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
     else if (L % kBK == 0) S = (int)std::min<int64_t>(L, (int64_t)1 << 26);
     else return MMP_EINVAL;  // longer blocks must be whole LDS stages
     if (L > ((int64_t)1 << 26)) return MMP_EINVAL;
-    bk = {L, S, !strict && lazy_block_ok(p, bu, bv, L), block_cost(S, L, false)};
+    bk = {L, S, ext || (!strict && lazy_block_ok(p, bu, bv, L)), ext, block_cost(S, L, false)};
   } else if (u != 0) {
-    bk = choose_kblock(p, bu, bv, lambda, k, strict);
+    bk = choose_kblock(p, bu, bv, k, strict, extended);
   }
 
   out->p = p;
@@ -255,6 +287,7 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
   out->kblock = bk.L;
   out->slots = bk.S;
   out->lazy = bk.lazy ? 1 : 0;
+  out->extended = bk.extended ? 1 : 0;
   out->tile = o.tile ? o.tile : pick_tile(bu * bv, m, n);
   Fp64Tile t = fp64_tile(out->tile, bu * bv);
   out->bm = fp64_bm(t);
@@ -263,7 +296,7 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
   out->q = 1.0 / (double)p;
   out->workspace_bytes = 0;
   out->est_seconds = fp64_seconds(m, n, k, bu * bv, bk.cost);
-  if (o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0 &&
+  if (o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0 && !extended &&
       int8_seconds(m, n, k, d8) < out->est_seconds) {
     std::memset(out, 0, sizeof(*out));
     return plan_int8();

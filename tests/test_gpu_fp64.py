@@ -188,3 +188,53 @@ def test_composite_modulus():
         B = gen.random_matrix(p % 89, 2, 90, 33, p)
         say("composite", p)
         assert_exact(run(p, A, B), oracle.mm_modp(p, A, B))
+
+
+# ------------------------------------------------------------------ extended block bound
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_extended_parity_all_word_pairs(p):
+    for (u, v) in SUPPORTED:
+        if pa.block_size(p, u, v) < 1:
+            continue
+        for (m, n, k) in [(17, 33, 29), (100, 70, 300), (130, 129, 67)]:
+            say("extended", p, u, v, m, n, k)
+            A = gen.random_matrix(p + m + 1, 1, m, k, p)
+            B = gen.random_matrix(p + n + 1, 2, k, n, p)
+            assert_exact(run(p, A, B, u, v, extended_block=True), oracle.mm_modp(p, A, B))
+
+
+@pytest.mark.parametrize("uv,bits", LIMITS)
+def test_extended_worst_case_at_bitsize_limit(uv, bits):
+    u, v = uv
+    p = gen.prev_prime(1 << bits)
+    a_ = pa.iroot_ceil(p, u)
+    x_low = ((p - 1) // a_) * a_ - 1 if u > 1 else p - 1
+    for fill in (p - 1, x_low):
+        m, n, k = 40, 36, 301
+        A = np.full((m, k), fill, dtype=np.uint64)
+        B = np.full((k, n), p - 1, dtype=np.uint64)
+        say("extended worst", u, v, p, fill, mmp.plan(p, m, n, k, u, v, extended_block=True))
+        assert_exact(run(p, A, B, u, v, extended_block=True), oracle.mm_modp(p, A, B))
+
+
+@pytest.mark.parametrize("p,u,v", [(33554393, 1, 1), (67108859, 1, 1), (1125899906842597, 2, 2),
+                                   (68719476731, 1, 3)])
+def test_extended_every_forced_kblock(p, u, v):
+    lam = pa.block_size(p, u, v)
+    m, n, k = 33, 47, 203
+    A = np.full((m, k), p - 1, dtype=np.uint64)
+    B = np.full((k, n), p - 1, dtype=np.uint64)
+    want = oracle.mm_modp(p, A, B)
+    Ls = [L for L in range(lam + 1, min(2 * lam + 3, 17))] + ([2 * (lam // 16) * 16] if lam >= 16 else [])
+    ok = 0
+    for L in Ls:
+        try:
+            mmp.plan(p, m, n, k, u, v, extended_block=True, force_kblock=L)
+        except mmp.MmpError:
+            continue
+        say("extended kblock", p, u, v, L)
+        assert_exact(run(p, A, B, u, v, extended_block=True, force_kblock=L), want)
+        ok += 1
+    assert ok >= 1

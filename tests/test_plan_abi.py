@@ -161,7 +161,7 @@ def test_forced_kblock():
 
 def test_reserved_options_rejected():
     o = mmp.MmpOpts()
-    o.reserved[2] = 1
+    o.reserved[1] = 1
     out = mmp.MmpPlan()
     assert mmp.lib().mmp_plan(33554393, 1, 1, 8, 8, 8, ctypes.byref(o), ctypes.byref(out)) == -1
 
@@ -262,3 +262,79 @@ def test_schedule_emulation_worst_case(p):
             c, peak = _emulate_entry(p, u, v, L, bool(pl["lazy"]), arow, bcol)
             assert c == (k * x * (p - 1)) % p
             assert peak <= TWO_T
+
+
+# ------------------------------------------------------------------ extended block bound
+# The opt-in extended bound accumulates over [-2^53, 2^53]: the in-loop
+# reduction is c = floor(fl(x q + K)), d = x - c p with K = floor(2^53/p) - 1.
+# Emulated exactly (one rounding for the fma), on worst-case words.
+
+
+def _biased_reduce(x, p, K):
+    q = 1.0 / p
+    assert abs(x) <= TWO_T
+    b = pa.fma(float(x), q, float(K))  # one rounding of x q + K
+    c = math.floor(b)
+    d = x - c * p
+    assert -K * p - p <= d < -K * p + 2 * p
+    assert -TWO_T <= d
+    return d
+
+
+def _emulate_extended(p, u, v, L, arow, bcol):
+    a_, b_ = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+    K = TWO_T // p - 1
+    k = len(arow)
+    out = [[0] * v for _ in range(u)]
+    lo = hi = 0
+    for i in range(u):
+        for j in range(v):
+            s = -K * p  # accumulator start, congruent to 0
+            for l0 in range(0, k, L):
+                for l in range(l0, min(k, l0 + L)):
+                    s += _words(arow[l], a_, u)[i] * _words(bcol[l], b_, v)[j]
+                    lo, hi = min(lo, s), max(hi, s)
+                s = _biased_reduce(s, p, K)
+            out[i][j] = s % p
+    c = 0
+    for i in reversed(range(u)):
+        si = 0
+        for j in reversed(range(v)):
+            si = (si * b_ + out[i][j]) % p
+        c = (c * a_ + si) % p
+    return c, lo, hi
+
+
+@pytest.mark.parametrize("p", [33554393, 67108859, 2147483647, 68719476731, 1125899906842597,
+                               4503599627370449])
+def test_extended_schedule_worst_case(p):
+    for (u, v) in SUPPORTED:
+        if pa.block_size(p, u, v) < 1:
+            continue
+        pl = mmp.plan(p, 64, 64, 4096, u, v, extended_block=True)
+        paper = mmp.plan(p, 64, 64, 4096, u, v)
+        L = pl["kblock"]
+        a_, b_ = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+        w = (p - 1) ** 2 if (u, v) == (1, 1) else a_ * b_
+        if not pl["extended"]:  # the paper's bound was the better one here
+            assert (pl["kblock"], pl["slots"]) == (paper["kblock"], paper["slots"])
+            continue
+        assert pl["lazy"] == 1
+        assert L * w + 4 * p - 1 <= 2 * TWO_T  # the extended bound
+        assert L >= paper["kblock"]  # never a worse block than the paper's
+        Lk = min(L, 40)
+        x_low = ((p - 1) // a_) * a_ - 1 if u > 1 else p - 1
+        for x in {p - 1, x_low}:
+            k = 3 * Lk + 1
+            c, lo, hi = _emulate_extended(p, u, v, Lk, [x] * k, [p - 1] * k)
+            assert c == (k * x * (p - 1)) % p
+            assert -TWO_T <= lo and hi <= TWO_T
+
+
+def test_extended_doubles_block_at_50_bits():
+    p = 1125899906842597
+    assert mmp.plan(p, 64, 64, 4096, 2, 2)["kblock"] == 4       # paper: lambda = 7, MFMA-aligned 4
+    pl = mmp.plan(p, 64, 64, 4096, 2, 2, extended_block=True)
+    assert pl["kblock"] == 8 and pl["lambda"] == 7              # extended: 11 allowed, 8 aligned
+    with pytest.raises(mmp.MmpError):
+        mmp.plan(p, 64, 64, 64, 2, 2, extended_block=True, strict_fmod=True)
