@@ -80,6 +80,83 @@ def cpu_baseline(prob, A, B, budget_s=12.0):
     }
 
 
+def serving(mmp, torch, gen, count, loads):
+    """Continuous-batching server on a Poisson stream of mixed products.
+
+    Requests: m, n, k log-uniform in [64, 4096], bitsize uniform in [20, 52],
+    p the largest prime below a random x of that bitsize, entries uniform in
+    [0, p) generated on the device.  First a closed-loop pass (all requests
+    at once) measures capacity; then open-loop passes submit at the given
+    fractions of it and report request latency (submission to completion)
+    percentiles beside throughput.
+    """
+    import threading
+
+    import numpy as np
+
+    reqs = gen.serve_stream(count, 1.0, seed=gen.BASE_SEED + 6)
+    ops = []
+    for i, r in enumerate(reqs):
+        pr = r.problem
+        g = torch.Generator(device="cuda")
+        g.manual_seed(pr.seed)
+        A = torch.randint(0, pr.p, (pr.m, pr.k), generator=g, device="cuda", dtype=torch.int64).double()
+        B = torch.randint(0, pr.p, (pr.k, pr.n), generator=g, device="cuda", dtype=torch.int64).double()
+        C = torch.empty((pr.m, pr.n), dtype=torch.float64, device="cuda")
+        ops.append((pr, A, B, C))
+    torch.cuda.synchronize()
+    flops = sum(2.0 * pr.m * pr.n * pr.k for pr, *_ in ops)
+    budget = 64 << 30
+
+    def run(arrivals):
+        lats = [0.0] * len(ops)
+        tickets = [None] * len(ops)
+        with mmp.Server(hbm_budget=budget, max_slots=64) as srv:
+            t0 = time.perf_counter()
+
+            def submitter():
+                for i, (pr, A, B, C) in enumerate(ops):
+                    if arrivals is not None:
+                        while time.perf_counter() - t0 < arrivals[i]:
+                            time.sleep(0)
+                    tickets[i] = srv.submit(A, B, C, pr.p)
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            for i in range(len(ops)):
+                while tickets[i] is None:
+                    time.sleep(1e-5)
+                st, lat = srv.wait(tickets[i], 600.0)
+                if st != 0:
+                    raise RuntimeError(f"request {i} failed: {st}")
+                lats[i] = lat
+            th.join()
+            wall = time.perf_counter() - t0
+            stats = srv.stats()
+        return np.array(lats), wall, stats
+
+    run(None)  # warm-up: kernels loaded, memory pool grown
+    lat, wall, stats = run(None)
+    capacity = len(ops) / wall
+    out = {"requests": len(ops), "capacity_req_per_s": round(capacity, 1),
+           "closed_loop_gflops": round(flops / wall / 1e9, 1),
+           "closed_loop_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+           "closed_loop_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+           "max_batch": stats["max_batch"], "loads": {}}
+    r = gen.raw_u64(gen.stream_key(gen.BASE_SEED + 6, 9), 0, len(ops)).astype(np.float64) / 2.0**64
+    gaps = -np.log1p(-np.minimum(r, 1 - 1e-16))  # unit-rate exponential
+    for f in loads:
+        arrivals = np.cumsum(gaps) / (f * capacity)
+        lat, wall, stats = run(arrivals)
+        out["loads"][str(f)] = {"rate_req_per_s": round(f * capacity, 1),
+                                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                                "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                                "throughput_gflops": round(flops / wall / 1e9, 1),
+                                "launches": stats["launches"], "max_batch": stats["max_batch"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +166,10 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="index inside the workload group")
     ap.add_argument("--form", type=int, default=0, help="0 auto, 1 FP64 words, 2 INT8 digits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", type=int, default=200,
+                    help="requests in the serving measurement (0: skip it)")
+    ap.add_argument("--serve-loads", default="0.8",
+                    help="comma-separated fractions of the measured capacity to offer")
     ap.add_argument("--extended", action="store_true",
                     help="FP64 form: allow the extended (signed-range) block bound")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -229,6 +310,10 @@ def main():
         "phases_ms_per_step": {k: round(v[1] / max(args.steps, 1), 4) for k, v in phases.items()},
         "source_digest": digest,
     }
+    if args.serve > 0:
+        log("serving ...")
+        del dA, dB, dC
+        out["serving"] = serving(mmp, torch, gen, args.serve, [float(x) for x in args.serve_loads.split(",")])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob, A, B)

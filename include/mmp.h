@@ -270,6 +270,23 @@ int mmp_server_stats(mmp_server *srv, mmp_server_stats_t *out);
 int mmp_plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k,
              const mmp_opts *opts, mmp_plan_t *out);
 
+/* Autotuner: times every candidate plan for this product shape on the
+ * current device (each admissible (u, v) with each tile and its block under
+ * the paper's bound, or the extended one if opts allows it, and the INT8-digit
+ * form) on scratch operands, and caches the fastest for the class of
+ * products with the same bitsize of p and the same ceil(log2) of m, n and k.
+ * Later AUTO plans (u = v = 0, no forced tile or block) of that class use it.
+ * *best receives the resulting plan, *tried the number of candidates timed.
+ * Synchronous; allocates 8 (mk + kn + mn) bytes of scratch. */
+int mmp_autotune(uint64_t p, int64_t m, int64_t n, int64_t k,
+                 const mmp_opts *opts, mmp_plan_t *best, int *tried);
+
+/* Tuning cache: forget all entries; write or read them as JSON (load returns
+ * the number of entries read or a negative status). */
+int mmp_tune_cache_clear(void);
+int mmp_tune_cache_save(const char *path);
+int mmp_tune_cache_load(const char *path);
+
 /* Device bytes a job occupies: its operands and result (8 (mk + kn + mn))
  * plus its word copies (FP64 words: 8 (u mk + v kn); INT8 digits:
  * da mk + db kn), per the storage cost of Section 3.3. */

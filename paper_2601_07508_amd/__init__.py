@@ -84,6 +84,17 @@ _lib.mmp_workspace_crt.argtypes = [_i64, _i64, _i64, _int, _int, ctypes.POINTER(
 _lib.mmp_workspace_crt.restype = _sz
 
 
+_lib.mmp_autotune.argtypes = [_u64, _i64, _i64, _i64, ctypes.POINTER(MmpOpts), ctypes.POINTER(MmpPlan),
+                              ctypes.POINTER(_int)]
+_lib.mmp_autotune.restype = _int
+_lib.mmp_tune_cache_clear.argtypes = []
+_lib.mmp_tune_cache_clear.restype = _int
+_lib.mmp_tune_cache_save.argtypes = [ctypes.c_char_p]
+_lib.mmp_tune_cache_save.restype = _int
+_lib.mmp_tune_cache_load.argtypes = [ctypes.c_char_p]
+_lib.mmp_tune_cache_load.restype = _int
+
+
 class MmpTimer(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", _i64), ("total_ms", _dbl)]
 
@@ -151,6 +162,30 @@ def plan(p: int, m: int, n: int, k: int, u: int = 0, v: int = 0, **opts) -> dict
     o = _opts(**opts)
     _check(_lib.mmp_plan(p, u, v, m, n, k, ctypes.byref(o), ctypes.byref(out)), "mmp_plan")
     return out.as_dict()
+
+
+def autotune(p: int, m: int, n: int, k: int, **opts):
+    """Times the candidate plans on the device; returns (plan, candidates timed)."""
+    out = MmpPlan()
+    tried = _int()
+    o = _opts(**opts)
+    _check(_lib.mmp_autotune(p, m, n, k, ctypes.byref(o), ctypes.byref(out), ctypes.byref(tried)), "mmp_autotune")
+    return out.as_dict(), tried.value
+
+
+def tune_cache_clear():
+    _lib.mmp_tune_cache_clear()
+
+
+def tune_cache_save(path: str):
+    _check(_lib.mmp_tune_cache_save(path.encode()), "mmp_tune_cache_save")
+
+
+def tune_cache_load(path: str) -> int:
+    n = _lib.mmp_tune_cache_load(path.encode())
+    if n < 0:
+        raise MmpError(n, "mmp_tune_cache_load")
+    return n
 
 
 def footprint(p: int, m: int, n: int, k: int, u: int = 0, v: int = 0, **opts) -> int:

@@ -55,6 +55,20 @@ int64_t extended_lambda(uint64_t p, int u, int v);
 int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
          mmp_plan_t* out);
 
+// Tuning cache (mmp_autotune fills it; AUTO plans read it).
+struct TunedChoice {
+  int form, u, v, tile;
+  int64_t kblock;
+  double ms;
+};
+void tune_store(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, const TunedChoice& c);
+bool tune_lookup(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, TunedChoice* c);
+void tune_clear();
+int tune_save(const char* path);
+int tune_load(const char* path);
+// Fill X (count binary64 values) with a hash of the index mod p (scratch inputs).
+int launch_fill_mod(double* X, int64_t count, uint64_t p, uint64_t seed, void* stream);
+
 // Kernel arguments for the FP64-word form.
 struct Fp64Args {
   const double* A;

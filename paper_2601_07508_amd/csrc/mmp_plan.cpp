@@ -8,7 +8,11 @@
 //   (u,v) choice by bitsize and cost            Section 3.3, Table tab.summary
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "mmp_internal.h"
 
@@ -161,7 +165,85 @@ int pick_tile(int uv, int64_t m, int64_t n) {
   return 3;
 }
 
+// ---------------------------------------------------------------- tuning cache
+// Fastest measured plan per (bitsize of p, ceil(log2) of m, n, k, extended
+// allowed); filled by mmp_autotune, read by AUTO plans.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, TunedChoice> g_tune;
+
+int log2_ceil(int64_t x) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < x) b++;
+  return b;
+}
+
 }  // namespace
+
+std::tuple<int, int, int, int, int> tune_key(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended) {
+  int bits = 0;
+  while (bits < 64 && (p >> bits) != 0) bits++;
+  return std::make_tuple(bits, log2_ceil(m), log2_ceil(n), log2_ceil(k), extended ? 1 : 0);
+}
+
+void tune_store(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, const TunedChoice& c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[tune_key(p, m, n, k, extended)] = c;
+}
+
+bool tune_lookup(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, TunedChoice* c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(p, m, n, k, extended));
+  if (it == g_tune.end()) return false;
+  *c = it->second;
+  return true;
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+int tune_save(const char* path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return MMP_EINVAL;
+  std::fprintf(f, "{\"entries\": [\n");
+  size_t i = 0;
+  for (auto& kv : g_tune) {
+    const auto& k = kv.first;
+    const TunedChoice& c = kv.second;
+    std::fprintf(f,
+                 "  {\"bits\": %d, \"lm\": %d, \"ln\": %d, \"lk\": %d, \"ext\": %d, \"form\": %d, \"u\": %d, "
+                 "\"v\": %d, \"tile\": %d, \"kblock\": %lld, \"ms\": %.6f}%s\n",
+                 std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), c.form, c.u, c.v,
+                 c.tile, (long long)c.kblock, c.ms, ++i < g_tune.size() ? "," : "");
+  }
+  std::fprintf(f, "]}\n");
+  std::fclose(f);
+  return MMP_OK;
+}
+
+int tune_load(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return MMP_ENOTFOUND;
+  char line[512];
+  int n = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    int bits, lm, ln, lk, ext, form, u, v, tile;
+    long long kb;
+    double ms;
+    if (std::sscanf(line,
+                    " {\"bits\": %d, \"lm\": %d, \"ln\": %d, \"lk\": %d, \"ext\": %d, \"form\": %d, \"u\": %d, "
+                    "\"v\": %d, \"tile\": %d, \"kblock\": %lld, \"ms\": %lf",
+                    &bits, &lm, &ln, &lk, &ext, &form, &u, &v, &tile, &kb, &ms) == 11) {
+      std::lock_guard<std::mutex> lk2(g_tune_mu);
+      g_tune[std::make_tuple(bits, lm, ln, lk, ext)] = TunedChoice{form, u, v, tile, (int64_t)kb, ms};
+      n++;
+    }
+  }
+  std::fclose(f);
+  return n;
+}
 
 int digits_for(uint64_t p) {
   int bits = 0;
@@ -181,15 +263,16 @@ size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k) {
   return (size_t)digits * (size_t)(m + n) * (size_t)kp;
 }
 
-int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
-         mmp_plan_t* out) {
+static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
+                     mmp_plan_t* out, bool use_tuned) {
   if (!out) return MMP_EINVAL;
   std::memset(out, 0, sizeof(*out));
   mmp_opts o;
   std::memset(&o, 0, sizeof(o));
   if (opts) o = *opts;
-  for (int r : o.reserved)
-    if (r != 0) return MMP_EINVAL;
+  if (opts)
+    for (int r : opts->reserved)
+      if (r != 0) return MMP_EINVAL;
   if (p < 5 || p >= kPMax) return MMP_EINVAL;
   if (m < 0 || n < 0 || k < 0) return MMP_EINVAL;
   if ((u == 0) != (v == 0)) return MMP_EINVAL;
@@ -236,6 +319,19 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
   // reproduces the bitsize ranges after Table tab.summary; ties go to the
   // orientation that puts extra words on the operand with the smaller outer
   // dimension (the concatenation rule of Section 3.2).
+  // A tuned choice for this class of products, if mmp_autotune measured one.
+  if (use_tuned && o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0) {
+    TunedChoice c;
+    if (tune_lookup(p, m, n, k, extended, &c)) {
+      mmp_opts o2 = o;
+      o2.form = c.form;
+      o2.tile = c.form == MMP_FORM_FP64_WORDS ? c.tile : 0;
+      o2.force_kblock = c.form == MMP_FORM_FP64_WORDS ? c.kblock : 0;
+      const int st = plan_impl(p, c.form == MMP_FORM_FP64_WORDS ? c.u : 0, c.form == MMP_FORM_FP64_WORDS ? c.v : 0,
+                               m, n, k, &o2, out, false);
+      if (st == MMP_OK) return MMP_OK;  // else the tuned block does not fit this p: plan afresh
+    }
+  }
   static const int cand[][2] = {{1, 1}, {1, 2}, {2, 1}, {1, 3}, {3, 1}, {2, 2},
                                 {1, 4}, {4, 1}, {2, 3}, {3, 2}, {2, 4}, {4, 2}};
   int bu = u, bv = v;
@@ -302,6 +398,10 @@ int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_op
     return plan_int8();
   }
   return MMP_OK;
+}
+
+int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts, mmp_plan_t* out) {
+  return plan_impl(p, u, v, m, n, k, opts, out, true);
 }
 
 }  // namespace mmp

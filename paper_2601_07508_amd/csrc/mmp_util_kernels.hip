@@ -172,7 +172,25 @@ __global__ void reduce_mod_kernel(const uint64_t* X, int64_t rows, int64_t cols,
   }
 }
 
+__global__ void fill_mod_kernel(double* X, int64_t count, uint64_t p, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;  // SplitMix64 finaliser
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    X[i] = (double)(z % p);
+  }
+}
+
 }  // namespace
+
+int launch_fill_mod(double* X, int64_t count, uint64_t p, uint64_t seed, void* stream) {
+  if (count <= 0) return 0;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_mod_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, X, count, p, seed);
+  return (int)hipGetLastError();
+}
 
 int launch_validate_bits(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld, int bits, int* flag,
                          void* stream) {

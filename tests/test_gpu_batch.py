@@ -204,3 +204,20 @@ def test_graph_capture_crt_and_batch_replays():
         x = torch.randn(1000, device="cuda").sum()
         torch.cuda.synchronize()
         del x
+
+
+def test_autotune_picks_a_correct_plan():
+    for p, shape in [(1125899906842597, (256, 256, 512)), (8388593, (512, 128, 300)), (68719476731, (200, 300, 700))]:
+        m, n, k = shape
+        mmp.tune_cache_clear()
+        best, tried = mmp.autotune(p, m, n, k)
+        say("autotune", p, shape, tried, best)
+        assert tried >= 2
+        pl = mmp.plan(p, m, n, k)  # AUTO now follows the tuned choice
+        assert (pl["form"], pl["u"], pl["v"], pl["tile"]) == (best["form"], best["u"], best["v"], best["tile"])
+        A = gen.random_matrix(4, 1, m, k, p)
+        B = gen.random_matrix(4, 2, k, n, p)
+        C = mmp.mm_modp(dev(A), dev(B), p)
+        torch.cuda.synchronize()
+        assert np.array_equal(C.cpu().numpy(), oracle.mm_modp(p, A, B).astype(np.float64))
+    mmp.tune_cache_clear()

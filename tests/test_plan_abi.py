@@ -338,3 +338,41 @@ def test_extended_doubles_block_at_50_bits():
     assert pl["kblock"] == 8 and pl["lambda"] == 7              # extended: 11 allowed, 8 aligned
     with pytest.raises(mmp.MmpError):
         mmp.plan(p, 64, 64, 64, 2, 2, extended_block=True, strict_fmod=True)
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    # An entry read from a file steers AUTO plans of its class; clearing it
+    # restores the planner's own choice.
+    p = 1125899906842597  # 50 bits
+    mmp.tune_cache_clear()
+    own = mmp.plan(p, 1000, 1000, 1000)
+    path = tmp_path / "tune.json"
+    path.write_text('{"entries": [\n'
+                    '  {"bits": 50, "lm": 10, "ln": 10, "lk": 10, "ext": 0, "form": 1, "u": 2, "v": 3, '
+                    '"tile": 3, "kblock": 400, "ms": 1.0}\n]}\n')
+    assert mmp.tune_cache_load(str(path)) == 1
+    pl = mmp.plan(p, 1000, 1000, 1000)
+    assert (pl["form"], pl["u"], pl["v"], pl["tile"], pl["kblock"]) == (1, 2, 3, 3, 400)
+    other = mmp.plan(p, 3000, 1000, 1000)  # a different class is unaffected
+    assert (other["form"], other["u"], other["v"]) == (own["form"], own["u"], own["v"])
+    out = tmp_path / "saved.json"
+    mmp.tune_cache_save(str(out))
+    assert '"u": 2, "v": 3' in out.read_text()
+    mmp.tune_cache_clear()
+    pl = mmp.plan(p, 1000, 1000, 1000)
+    assert (pl["form"], pl["u"], pl["v"]) == (own["form"], own["u"], own["v"])
+
+
+def test_tune_cache_entry_that_does_not_fit_is_ignored(tmp_path):
+    # a tuned block longer than this p's bound falls back to a fresh plan
+    p = 1125899906842597
+    path = tmp_path / "tune.json"
+    path.write_text('{"entries": [\n'
+                    '  {"bits": 50, "lm": 6, "ln": 6, "lk": 6, "ext": 0, "form": 1, "u": 2, "v": 2, '
+                    '"tile": 1, "kblock": 64, "ms": 1.0}\n]}\n')
+    mmp.tune_cache_clear()
+    assert mmp.tune_cache_load(str(path)) == 1
+    pl = mmp.plan(p, 64, 64, 64)
+    assert not (pl["form"] == 1 and (pl["u"], pl["v"]) == (2, 2) and pl["kblock"] == 64)
+    assert pl["form"] == 2 or pa.block_size(p, pl["u"], pl["v"]) >= pl["kblock"] or pl["extended"]
+    mmp.tune_cache_clear()
