@@ -157,6 +157,90 @@ def serving(mmp, torch, gen, count, loads):
     return out
 
 
+def _time(torch, fn, warmup, steps):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_crt(args, mmp, torch, gen):
+    """One integer pair against 32 primes of 31..50 bits (the CRT job)."""
+    import numpy as np
+
+    import oracle
+
+    job = gen.crt_job()
+    A, B = job.a(), job.b()
+    dA = torch.from_numpy(A.astype(np.int64)).cuda()
+    dB = torch.from_numpy(B.astype(np.int64)).cuda()
+    outs = [torch.empty((job.m, job.n), dtype=torch.float64, device="cuda") for _ in job.primes]
+    ms = _time(torch, lambda: mmp.mm_modp_crt(dA, dB, job.primes, outs, job.bits), args.warmup, args.steps)
+    mmp.timers_read(reset=True)
+    mmp.timers_enable(True)
+    mmp.mm_modp_crt(dA, dB, job.primes, outs, job.bits)
+    torch.cuda.synchronize()
+    mmp.timers_enable(False)
+    phases = mmp.timers_read(reset=True)
+    rr = np.array([0, job.m - 1, 77], dtype=np.int64)
+    cc = np.array([5, job.n - 1, 0], dtype=np.int64)
+    for p, C in zip(job.primes, outs):
+        want = oracle.mm_modp_entries(p, A, B, rr, cc).astype(np.float64)
+        got = C[torch.from_numpy(rr).cuda(), torch.from_numpy(cc).cuda()].cpu().numpy()
+        if not np.array_equal(got, want):
+            log("RESULT MISMATCH", p)
+            sys.exit(1)
+    mnk = float(job.m) * job.n * job.k
+    d = (job.bits + 1 + 7) // 8
+    gemm_ms = phases.get("crt_gemm", (1, 0.0))[1]
+    print(json.dumps({
+        "metric": "effective 2mnk GFLOP/s over all moduli of the CRT job",
+        "value": round(len(job.primes) * 2 * mnk / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s",
+        "ms_per_step": round(ms, 4), "primes": len(job.primes), "entry_bits": job.bits,
+        "config": {"workload": f"CRT {job.m}x{job.n}x{job.k}, entries < 2^{job.bits}, "
+                               f"{len(job.primes)} primes of 31..50 bits"},
+        "roofline": {"bound": "mfma", "kernel": "crt_gemm_kernel", "kernel_ms": round(gemm_ms, 4),
+                     "achieved": round(2 * d * d * mnk / (gemm_ms * 1e-3) / 1e12, 2) if gemm_ms else None,
+                     "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s"},
+        "phases_ms": {k: round(v[1], 4) for k, v in phases.items()}}), flush=True)
+
+
+def sweep_bits(args, mmp, torch, gen):
+    """Both word forms on one shape for each bitsize: which one wins."""
+    import numpy as np
+
+    base = gen.config_problems(args.config)[args.variant]
+    for b in [int(x) for x in args.sweep_bits.split(",")]:
+        p = gen.largest_prime_below_pow2(b)
+        A = gen.random_matrix(b, 1, base.m, base.k, p)
+        B = gen.random_matrix(b, 2, base.k, base.n, p)
+        dA = torch.from_numpy(A.astype(np.float64)).cuda()
+        dB = torch.from_numpy(B.astype(np.float64)).cuda()
+        res = {}
+        outs = {}
+        for name, kw in (("fp64_words", {"form": 1}), ("fp64_words_extended", {"form": 1, "extended_block": True}),
+                         ("int8_digits", {"form": 2})):
+            C = torch.empty((base.m, base.n), dtype=torch.float64, device="cuda")
+            pl = mmp.plan(p, base.m, base.n, base.k, **kw)
+            ms = _time(torch, lambda: mmp.mm_modp_async(dA, dB, C, p, stream=torch.cuda.current_stream(), **kw),
+                       2, max(3, args.steps // 4))
+            res[name] = {"ms": round(ms, 4), "eff_gflops": round(2.0 * base.m * base.n * base.k / ms / 1e6, 1),
+                         "uv": [pl["u"], pl["v"]], "digits": pl["digits_a"], "kblock": pl["kblock"]}
+            outs[name] = C
+        same = all(torch.equal(outs["int8_digits"], c) for c in outs.values())
+        win = min(res, key=lambda k: res[k]["ms"])
+        print(json.dumps({"bits": b, "p": p, "shape": [base.m, base.n, base.k], "forms": res, "winner": win,
+                          "identical_outputs": bool(same)}), flush=True)
+        if not same:
+            sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +254,10 @@ def main():
                     help="requests in the serving measurement (0: skip it)")
     ap.add_argument("--serve-loads", default="0.8",
                     help="comma-separated fractions of the measured capacity to offer")
+    ap.add_argument("--crt", action="store_true",
+                    help="time the multi-modular job (2048^3 integers < 2^60 against 32 primes) instead")
+    ap.add_argument("--sweep-bits", default="",
+                    help="comma-separated bitsizes: time both forms on the workload's shape for each")
     ap.add_argument("--extended", action="store_true",
                     help="FP64 form: allow the extended (signed-range) block bound")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -204,6 +292,11 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_bytes, "ms": ms,
                           "GB/s (read+write)": 2 * args.copy_bytes / ms / 1e6}), flush=True)
         return
+
+    if args.crt:
+        return bench_crt(args, mmp, torch, gen)
+    if args.sweep_bits:
+        return sweep_bits(args, mmp, torch, gen)
 
     prob = gen.config_problems(args.config)[args.variant]
     if args.form == 2:  # the INT8-digit form takes no word counts

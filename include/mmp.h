@@ -94,7 +94,11 @@ typedef struct {
                              with L w + 4p - 1 <= 2^(t+1), about twice the
                              paper's lambda (project-derived bound; w is the
                              paper's per-term bound).  0: the paper's bound. */
-  int reserved[3];        /* must be zero */
+  int splits;             /* split-K: 0 = planner's choice (used when a
+                             product has too few output tiles for the chip
+                             and a long k), 1 = never, > 1 = that many
+                             k-ranges; their residues are added mod p */
+  int reserved[2];        /* must be zero */
 } mmp_opts;
 
 /* What the planner decided for one product (mmp_plan fills it). */
@@ -118,6 +122,7 @@ typedef struct {
   int64_t kblock_int8;    /* INT8 form: k-terms per int32 accumulation block */
   double q;               /* fl(1/p) */
   double est_seconds;     /* planner's cost-model estimate (0 if unknown) */
+  int splits;             /* split-K k-ranges (1: none) */
   size_t workspace_bytes; /* device workspace the call needs */
 } mmp_plan_t;
 

@@ -36,7 +36,7 @@ STATUS = {0: "MMP_OK", -1: "MMP_EINVAL", -2: "MMP_EBOUND", -3: "MMP_ERANGE", -4:
 class MmpOpts(ctypes.Structure):
     _fields_ = [("form", _int), ("validate_entries", _int), ("tile", _int), ("strict_fmod", _int),
                 ("force_kblock", _i64), ("workspace", _vp), ("workspace_bytes", _sz), ("extended_block", _int),
-                ("reserved", _int * 3)]
+                ("splits", _int), ("reserved", _int * 2)]
 
 
 class MmpPlan(ctypes.Structure):
@@ -44,7 +44,8 @@ class MmpPlan(ctypes.Structure):
                 ("lambda_", _i64), ("kblock", _i64), ("slots", _int), ("lazy", _int), ("extended", _int),
                 ("tile", _int),
                 ("bm", _int), ("bn", _int), ("bk", _int), ("digits_a", _int), ("digits_b", _int),
-                ("kblock_int8", _i64), ("q", _dbl), ("est_seconds", _dbl), ("workspace_bytes", _sz)]
+                ("kblock_int8", _i64), ("q", _dbl), ("est_seconds", _dbl), ("splits", _int),
+                ("workspace_bytes", _sz)]
 
     def as_dict(self):
         d = {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -142,8 +143,9 @@ def strerror(status: int) -> str:
 
 
 def _opts(form=FORM_AUTO, force_kblock=0, validate_entries=False, tile=0, strict_fmod=False,
-          workspace=None, extended_block=False):
+          workspace=None, extended_block=False, splits=0):
     o = MmpOpts()
+    o.splits = splits
     o.extended_block = 1 if extended_block else 0
     o.form = form
     o.force_kblock = force_kblock

@@ -111,7 +111,10 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
   int job = 0;
   while (job + 1 < bt.njobs && (int)blockIdx.x >= bt.tile_start[job + 1]) job++;
   const Fp64Args& a = bt.job[job];
-  const int local_bid = (int)blockIdx.x - bt.tile_start[job];
+  // split-K: tiles of one k-range are consecutive; split index major
+  const int tiles = (int)(((a.m + 2 * TM * 16 - 1) / (2 * TM * 16)) * ((a.n + 2 * TN * 16 - 1) / (2 * TN * 16)));
+  const int split = ((int)blockIdx.x - bt.tile_start[job]) / tiles;
+  const int local_bid = ((int)blockIdx.x - bt.tile_start[job]) - split * tiles;
   constexpr int BM = 2 * TM * 16;
   constexpr int BN = 2 * TN * 16;
   constexpr int LDA = kBK + kPadA;
@@ -209,7 +212,11 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
         for (int y = 0; y < TN; y++) acc[i][j][x][y] = (d4){a.acc_init, a.acc_init, a.acc_init, a.acc_init};
 
   const double p = a.p, q = a.q, bias = a.bias;
-  const int64_t nstages = (a.k + KR - 1) / KR;
+  const int64_t nstages_all = (a.k + KR - 1) / KR;
+  // this split's stages: [s_begin, s_end)
+  const int64_t per_split = (nstages_all + a.splits - 1) / a.splits;
+  const int64_t s_begin = (int64_t)split * per_split;
+  const int64_t s_end = s_begin + per_split < nstages_all ? s_begin + per_split : nstages_all;
   const int lrow = lane & 15, lk = lane >> 4;
 
   // In-loop reduction of every accumulator (Alg. 1).  The correction-free
@@ -245,12 +252,12 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
   };
 
   int stage_in_block = 0;
-  if (nstages > 0) load_stage(0);
-  for (int64_t s = 0; s < nstages; s++) {
+  if (s_begin < s_end) load_stage(s_begin * KR);
+  for (int64_t s = s_begin; s < s_end; s++) {
     __syncthreads();  // previous stage's MFMA reads are done
     store_stage();
     __syncthreads();
-    if (s + 1 < nstages) load_stage((s + 1) * KR);  // in flight during the MFMAs
+    if (s + 1 < s_end) load_stage((s + 1) * KR);  // in flight during the MFMAs
 
 #pragma unroll
     for (int ks = 0; ks < kBK / 4; ks++) {
@@ -304,7 +311,12 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
             si = addmod(mulmod(a.beta, si, p, q), fmod_full(acc[i][j][x][y][r], p, q), p);
           c = (i == U - 1) ? si : addmod(mulmod(a.alpha, c, p, q), si, p);
         }
-        if (row < a.m && col < a.n) a.C[row * a.ldc + col] = c + 0.0;  // +0.0: canonical zero
+        if (row < a.m && col < a.n) {
+          if (a.splits == 1)
+            a.C[row * a.ldc + col] = c + 0.0;  // +0.0: canonical zero
+          else
+            a.partial[((int64_t)split * a.m + row) * a.n + col] = c;  // residue of this k-range
+        }
       }
     }
   }
@@ -320,7 +332,7 @@ struct TileOf {
 // Tiles of one product for a given shape.
 template <int BM, int BN>
 inline int64_t tiles_of(const Fp64Args& a) {
-  return ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN);
+  return ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN) * a.splits;
 }
 
 template <int U, int V, int ID, int FE>

@@ -153,6 +153,8 @@ struct GemmArgs {
   int64_t m, n, kp, ldc;
   double p, q;
   int64_t stages_per_block;  // LDS stages (64 k-terms each) between folds
+  int splits;                // split-K: k-ranges (1: none)
+  double* partial;           // splits > 1: residues per k-range, [splits][m][n]
 };
 
 __device__ __forceinline__ void tile_coords(int bid, int nb, int nbm, int nbn, int& tmi, int& tni) {
@@ -220,6 +222,7 @@ __device__ __forceinline__ void wait_vm() {
 template <int D, class S, class Fold>
 __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, const int8_t* __restrict__ Bd,
                                                 int64_t m, int64_t n, int64_t kp, int64_t m0, int64_t n0,
+                                                int64_t st_begin, int64_t st_end,
                                                 int64_t stages_per_block, DigitRing<D, S::BM, S::BN>& sm,
                                                 int4v (&acc)[2 * D - 1][S::TM][S::TN], Fold fold) {
   constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
@@ -256,7 +259,6 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
       dst_row[e] = BM + 16 * g;
     }
   }
-  const int64_t nstages = kp / 64;
   auto issue = [&](int64_t st) {
     const int b = (int)(st & 1);
 #pragma unroll
@@ -267,9 +269,9 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
   };
 
   const int lrow = lane & 15, lq = lane >> 4;
-  if (nstages > 0) issue(0);
+  if (st_begin < st_end) issue(st_begin);
   int64_t in_block = 0;
-  for (int64_t st = 0; st < nstages; st++) {
+  for (int64_t st = st_begin; st < st_end; st++) {
     // This wave's copies of stage st are complete; the barrier extends that
     // to every wave and ends the reads of stage st - 1, whose buffer the
     // next copies overwrite.  A bare barrier: a fence here would also wait
@@ -279,7 +281,7 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (st + 1 < nstages) issue(st + 1);
+    if (st + 1 < st_end) issue(st + 1);
     const int b = (int)(st & 1);
     int4v bf[D][TN];
 #pragma unroll
@@ -324,10 +326,15 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
   int job = 0;
   while (job + 1 < bt.njobs && (int)blockIdx.x >= bt.tile_start[job + 1]) job++;
   const GemmArgs& a = bt.job[job];
-  const int local_bid = (int)blockIdx.x - bt.tile_start[job];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
+  // split-K: tiles of one k-range are consecutive; split index major
+  const int split = ((int)blockIdx.x - bt.tile_start[job]) / (nbm * nbn);
+  const int local_bid = ((int)blockIdx.x - bt.tile_start[job]) - split * nbm * nbn;
+  const int64_t nst = a.kp / kBK8, per_split = (nst + a.splits - 1) / a.splits;
+  const int64_t st_begin = (int64_t)split * per_split;
+  const int64_t st_end = st_begin + per_split < nst ? st_begin + per_split : nst;
   int tmi, tni;
   tile_coords(local_bid, nbm * nbn, nbm, nbn, tmi, tni);
   const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
@@ -371,7 +378,7 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
 #pragma unroll
         for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
   };
-  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.stages_per_block, sm, acc, fold);
+  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, st_begin, st_end, a.stages_per_block, sm, acc, fold);
 
   // 16x16x64 INT8 MFMA output layout: D[i][j] is value (i & 3) of lane j + 16 (i >> 2).
   const int lrow = lane & 15;
@@ -383,7 +390,12 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
-        if (row < a.m && col < a.n) a.C[row * a.ldc + col] = F[x][y][r] + 0.0;
+        if (row < a.m && col < a.n) {
+          if (a.splits == 1)
+            a.C[row * a.ldc + col] = F[x][y][r] + 0.0;
+          else
+            a.partial[((int64_t)split * a.m + row) * a.n + col] = F[x][y][r];
+        }
       }
     }
 }
@@ -425,7 +437,7 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
 #pragma unroll
       for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
   // one int32 block covers the whole k (checked by the launcher)
-  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, a.kp / kBK8 + 1, sm, acc, [] {});
+  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, 0, a.kp / kBK8, a.kp / kBK8 + 1, sm, acc, [] {});
 
   const int lrow = lane & 15;
   for (int pi = 0; pi < a.nprimes; pi++) {

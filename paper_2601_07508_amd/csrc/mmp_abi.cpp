@@ -166,6 +166,7 @@ Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, c
   a.KR = (pl.slots <= kBK) ? (kBK / pl.slots) * (int)pl.kblock : kBK;
   a.stages_per_block = pl.slots >= kBK ? pl.slots / kBK : 1;
   a.lazy = pl.lazy;
+  a.splits = 1;
   if (pl.extended) {
     const uint64_t K = (kTwoT / pl.p) - 1;  // K p <= 2^t - p
     a.bias = (double)K;
@@ -192,6 +193,7 @@ Int8Args make_int8_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, c
   g.q = pl.q;
   g.kblock = pl.kblock_int8;
   g.work = work;
+  g.splits = 1;
   return g;
 }
 
@@ -255,22 +257,33 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
     if (opts && opts->validate_entries)
       if (int st = validate_product_entries(p, m, n, k, A, lda, B, ldb, stream)) return st;
 
+    void* work = nullptr;
+    bool owned = false;
+    if (int st = acquire_workspace(pl.workspace_bytes, opts, stream, &work, &owned)) return st;
+    // split-K residues go after the digit planes (INT8) or fill the workspace (FP64)
+    const size_t planes = pl.form == MMP_FORM_INT8_WORDS
+                              ? (int8_workspace_bytes(pl.digits_a, m, n, k) + 255) / 256 * 256 : 0;
+    double* partial = pl.splits > 1 ? (double*)((char*)work + planes) : nullptr;
+    int e;
     if (pl.form == MMP_FORM_INT8_WORDS) {
-      void* work = nullptr;
-      bool owned = false;
-      if (int st = acquire_workspace(pl.workspace_bytes, opts, stream, &work, &owned)) return st;
       Int8Args g = make_int8_args(pl, m, n, k, A, lda, B, ldb, C, ldc, (int8_t*)work);
-      int e = launch_int8_digitize(pl.digits_a, g, stream);
+      g.splits = pl.splits;
+      g.partial = partial;
+      e = launch_int8_digitize(pl.digits_a, g, stream);
       if (!e) e = launch_int8_gemm(pl.digits_a, &g, 1, stream);
-      const int st = hip_status(e);
-      const int st2 = release_workspace(work, owned, stream);
-      return st ? st : st2;
+    } else {
+      Fp64Batch b;
+      std::memset(&b, 0, sizeof(b));
+      b.njobs = 1;
+      b.job[0] = make_fp64_args(pl, m, n, k, A, lda, B, ldb, C, ldc);
+      b.job[0].splits = pl.splits;
+      b.job[0].partial = partial;
+      e = launch_fp64_words(pl.u, pl.v, pl.tile, b, stream);
     }
-    Fp64Batch b;
-    std::memset(&b, 0, sizeof(b));
-    b.njobs = 1;
-    b.job[0] = make_fp64_args(pl, m, n, k, A, lda, B, ldb, C, ldc);
-    return hip_status(launch_fp64_words(pl.u, pl.v, pl.tile, b, stream));
+    if (!e && pl.splits > 1) e = launch_splitk_reduce(partial, pl.splits, m, n, (double)p, C, ldc, stream);
+    const int st = hip_status(e);
+    const int st2 = release_workspace(work, owned, stream);
+    return st ? st : st2;
   } catch (...) {
     return MMP_EINVAL;
   }

@@ -39,6 +39,12 @@ struct Planned {
 int plan_batch(const mmp_job* jobs, int count, const mmp_opts* opts, std::vector<Planned>* out,
                size_t* ws_total) {
   if (count < 0 || (count > 0 && !jobs)) return MMP_EINVAL;
+  // batched products run one k-range each (their many tiles fill the chip)
+  mmp_opts o1;
+  std::memset(&o1, 0, sizeof(o1));
+  if (opts) o1 = *opts;
+  o1.splits = 1;
+  opts = &o1;
   out->clear();
   out->reserve(count);
   size_t ws = 0;
@@ -248,6 +254,7 @@ int mm_modp_crt(const mmp_opts* opts, const uint64_t* A, int64_t lda, const uint
         mmp_opts o;
         std::memset(&o, 0, sizeof(o));
         if (opts) o.form = opts->form;
+        o.splits = 1;
         o.workspace = (char*)work + per * i + align_up(8 * (size_t)(m * k + k * n));
         o.workspace_bytes = align_up(7 * (size_t)(m + n) * kp);
         st = mm_modp_async(&o, jobs[i].p, 0, 0, m, n, k, jobs[i].A, jobs[i].lda, jobs[i].B, jobs[i].ldb,

@@ -76,8 +76,10 @@ int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* str
     a.p = (double)g.p;
     a.q = g.q;
     a.stages_per_block = g.kblock / kBK8;
+    a.splits = g.splits < 1 ? 1 : g.splits;
+    a.partial = g.partial;
     b.tile_start[j] = (int)total;
-    total += ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN);
+    total += ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN) * a.splits;
     if (total > 0x7fffffff) return (int)hipErrorInvalidValue;
   }
   b.tile_start[njobs] = (int)total;

@@ -83,6 +83,8 @@ struct Fp64Args {
   int lazy;              // in-loop reductions without corrections
   double bias;           // K in the in-loop reduction c = floor(x q + K) (0, or floor(2^t / p) - 1)
   double acc_init;       // accumulator start value: -K p (congruent to 0)
+  int splits;            // split-K: k-ranges of this product (1: none)
+  double* partial;       // splits > 1: residues per k-range, [splits][m][n]
 };
 
 // INT8-digit form: digit planes in a device workspace, then the digit GEMM.
@@ -99,7 +101,14 @@ struct Int8Args {
   int8_t* work;      // D (m + n) kp bytes: planes of A, then of B^T
   const int8_t* resident_a;  // optional ready planes of A (then A is not digitised)
   const int8_t* resident_b;  // optional ready planes of B^T
+  int splits;                // split-K: k-ranges (1: none)
+  double* partial;           // splits > 1: residues per k-range, [splits][m][n]
 };
+// C = sum over the splits of partial[s] mod p (each partial in [0, p)).
+int launch_splitk_reduce(const double* partial, int splits, int64_t m, int64_t n, double p, double* C, int64_t ldc,
+                         void* stream);
+// Split count for a product of `tiles` output tiles and `stages` k-stages.
+int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split);
 // Digit planes of one operand side into out (side 0: A rows -> [D][rows][kp];
 // side 1: B columns -> [D][cols][kp]).
 int launch_int8_digitize_side(int digits, int side, const double* X, int64_t rows, int64_t cols, int64_t ld,

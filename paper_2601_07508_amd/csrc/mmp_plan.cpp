@@ -279,7 +279,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   if (u != 0 && !supported_words(u, v)) return MMP_EINVAL;
   if (o.form != MMP_FORM_AUTO && o.form != MMP_FORM_FP64_WORDS && o.form != MMP_FORM_INT8_WORDS)
     return MMP_EINVAL;
-  if (o.force_kblock < 0 || o.tile < 0 || o.tile > 3) return MMP_EINVAL;
+  if (o.force_kblock < 0 || o.tile < 0 || o.tile > 3 || o.splits < 0 || o.splits > 64) return MMP_EINVAL;
 
   const bool strict = o.strict_fmod != 0;
   const bool extended = o.extended_block != 0;
@@ -300,7 +300,10 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     out->q = 1.0 / (double)p;
     out->bk = 64;
     out->est_seconds = int8_seconds(m, n, k, d8);
-    out->workspace_bytes = int8_workspace_bytes(d8, m, n, k);
+    const int64_t tiles = cdiv(m, 64) * cdiv(n, 64);
+    out->splits = o.splits ? o.splits : choose_splits(tiles, cdiv(k, 64), 32);
+    out->workspace_bytes = (int8_workspace_bytes(d8, m, n, k) + 255) / 256 * 256;
+    if (out->splits > 1) out->workspace_bytes += 8 * (size_t)out->splits * (size_t)m * (size_t)n;
     return MMP_OK;
   };
   if (o.form == MMP_FORM_INT8_WORDS) {
@@ -390,8 +393,13 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->bn = fp64_bn(t);
   out->bk = kBK;
   out->q = 1.0 / (double)p;
-  out->workspace_bytes = 0;
   out->est_seconds = fp64_seconds(m, n, k, bu * bv, bk.cost);
+  {
+    const int64_t KR = bk.S <= kBK ? (kBK / bk.S) * bk.L : kBK;
+    const int64_t tiles = cdiv(m, out->bm) * cdiv(n, out->bn);
+    out->splits = o.splits ? o.splits : choose_splits(tiles, cdiv(k, KR), 64);
+    out->workspace_bytes = out->splits > 1 ? 8 * (size_t)out->splits * (size_t)m * (size_t)n : 0;
+  }
   if (o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0 && !extended &&
       int8_seconds(m, n, k, d8) < out->est_seconds) {
     std::memset(out, 0, sizeof(*out));

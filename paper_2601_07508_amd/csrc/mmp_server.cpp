@@ -399,7 +399,10 @@ int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
     if (int st = check_product_args(j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc)) return st;
     Request r;
     r.job = j;
-    if (int st = mmp::plan(j.p, j.u, j.v, j.m, j.n, j.k, nullptr, &r.plan)) return st;
+    mmp_opts o1;
+    std::memset(&o1, 0, sizeof(o1));
+    o1.splits = 1;  // requests run whole; concurrency comes from the mix
+    if (int st = mmp::plan(j.p, j.u, j.v, j.m, j.n, j.k, &o1, &r.plan)) return st;
     std::lock_guard<std::mutex> lk(s->mu);
     if (r.plan.form == MMP_FORM_INT8_WORDS) {
       const int64_t kp = (j.k + 63) / 64 * 64;

@@ -172,6 +172,21 @@ __global__ void reduce_mod_kernel(const uint64_t* X, int64_t rows, int64_t cols,
   }
 }
 
+__global__ void splitk_reduce_kernel(const double* P, int splits, int64_t m, int64_t n, double p, double* C,
+                                     int64_t ldc) {
+  const int64_t total = m * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < splits; t++) {  // residues in [0, p): exact modular adds
+      s += P[t * total + i];
+      s = (s >= p) ? s - p : s;
+    }
+    const int64_t r = i / n, c = i - (i / n) * n;
+    C[r * ldc + c] = s + 0.0;
+  }
+}
+
 __global__ void fill_mod_kernel(double* X, int64_t count, uint64_t p, uint64_t seed) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -184,6 +199,28 @@ __global__ void fill_mod_kernel(double* X, int64_t count, uint64_t p, uint64_t s
 }
 
 }  // namespace
+
+int launch_splitk_reduce(const double* partial, int splits, int64_t m, int64_t n, double p, double* C, int64_t ldc,
+                         void* stream) {
+  if (m <= 0 || n <= 0) return 0;
+  const int64_t total = m * n;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  TimerTok* t = timer_begin("splitk_reduce");
+  hipExtLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                        timer_start(t), timer_stop(t), 0, partial, splits, m, n, p, C, ldc);
+  const int e = (int)hipGetLastError();
+  timer_commit(t, e);
+  return e;
+}
+
+int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split) {
+  // enough workgroups for 256 CUs (two per CU), each split a sizeable k-range
+  if (tiles >= 512 || stages < 2 * min_stages_per_split) return 1;
+  int64_t s = (512 + tiles - 1) / tiles;
+  s = std::min<int64_t>(s, stages / min_stages_per_split);
+  s = std::min<int64_t>(s, 64);
+  return (int)std::max<int64_t>(s, 1);
+}
 
 int launch_fill_mod(double* X, int64_t count, uint64_t p, uint64_t seed, void* stream) {
   if (count <= 0) return 0;

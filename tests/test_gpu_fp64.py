@@ -238,3 +238,15 @@ def test_extended_every_forced_kblock(p, u, v):
         assert_exact(run(p, A, B, u, v, extended_block=True, force_kblock=L), want)
         ok += 1
     assert ok >= 1
+
+
+@pytest.mark.parametrize("splits", [2, 3, 7])
+def test_split_k_fp64(splits):
+    # k-ranges produce exact residues that are added mod p: result unchanged
+    for p, (u, v) in [(33554393, (1, 1)), (1125899906842597, (2, 2)), (4503599627370449, (2, 3))]:
+        m, n, k = 70, 90, 1000 + 37
+        A = gen.random_matrix(splits, 1, m, k, p)
+        B = gen.random_matrix(splits, 2, k, n, p)
+        say("splitk fp64", p, u, v, splits)
+        assert mmp.plan(p, m, n, k, u, v, splits=splits)["splits"] == splits
+        assert_exact(run(p, A, B, u, v, splits=splits), oracle.mm_modp(p, A, B))

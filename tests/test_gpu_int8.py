@@ -150,3 +150,19 @@ def test_int8_equals_fp64_form(p):
     mmp.mm_modp_async(dev(A), dev(B), C64, p, form=mmp.FORM_FP64_WORDS)
     torch.cuda.synchronize()
     assert np.array_equal(C8, C64.cpu().numpy())
+
+
+@pytest.mark.parametrize("splits", [2, 5, 8])
+def test_split_k_int8(splits):
+    for p in (65521, 2147483647, 4503599627370449):
+        m, n, k = 70, 90, 2000 + 37
+        A = gen.random_matrix(splits, 1, m, k, p)
+        B = gen.random_matrix(splits, 2, k, n, p)
+        say("splitk int8", p, splits)
+        assert mmp.plan(p, m, n, k, form=INT8, splits=splits)["splits"] == splits
+        assert_exact(run(p, A, B, splits=splits), oracle.mm_modp(p, A, B))
+    # with folds inside each k-range as well
+    p = 1125899906842597
+    A = gen.random_matrix(1, 1, 40, 3000, p)
+    B = gen.random_matrix(1, 2, 3000, 30, p)
+    assert_exact(run(p, A, B, splits=splits, force_kblock=128), oracle.mm_modp(p, A, B))

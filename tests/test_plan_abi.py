@@ -161,7 +161,7 @@ def test_forced_kblock():
 
 def test_reserved_options_rejected():
     o = mmp.MmpOpts()
-    o.reserved[1] = 1
+    o.reserved[0] = 1
     out = mmp.MmpPlan()
     assert mmp.lib().mmp_plan(33554393, 1, 1, 8, 8, 8, ctypes.byref(o), ctypes.byref(out)) == -1
 
