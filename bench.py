@@ -225,6 +225,7 @@ def sweep_bits(args, mmp, torch, gen):
         res = {}
         outs = {}
         for name, kw in (("fp64_words", {"form": 1}), ("fp64_words_extended", {"form": 1, "extended_block": True}),
+                         ("fp64_words_centered", {"form": 1, "centered_words": True}),
                          ("int8_digits", {"form": 2})):
             C = torch.empty((base.m, base.n), dtype=torch.float64, device="cuda")
             pl = mmp.plan(p, base.m, base.n, base.k, **kw)
@@ -260,6 +261,8 @@ def main():
                     help="comma-separated bitsizes: time both forms on the workload's shape for each")
     ap.add_argument("--extended", action="store_true",
                     help="FP64 form: allow the extended (signed-range) block bound")
+    ap.add_argument("--centered", action="store_true",
+                    help="FP64 form: centered words and their block bound")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the product, time a plain device copy of this many bytes "
                          "(the reference kernel for scaling HBM counters)")
@@ -301,7 +304,8 @@ def main():
     prob = gen.config_problems(args.config)[args.variant]
     if args.form == 2:  # the INT8-digit form takes no word counts
         prob.u = prob.v = 0
-    plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, form=args.form, extended_block=args.extended)
+    plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, form=args.form, extended_block=args.extended,
+                    centered_words=args.centered)
     log("workload", prob.tag, "plan", plan)
 
     A = prob.a()
@@ -313,7 +317,7 @@ def main():
 
     def step():
         mmp.mm_modp_async(dA, dB, dC, prob.p, prob.u, prob.v, stream=stream, form=args.form,
-                          extended_block=args.extended)
+                          extended_block=args.extended, centered_words=args.centered)
 
     for _ in range(args.warmup):
         step()
@@ -397,6 +401,7 @@ def main():
             "m": prob.m, "n": prob.n, "k": prob.k, "p": prob.p, "bits": prob.p.bit_length(),
             "u": plan["u"], "v": plan["v"], "lambda": plan["lambda"], "kblock": plan["kblock"],
             "digits": plan["digits_a"], "extended_block": bool(plan["extended"]),
+            "centered_words": bool(plan["centered"]),
             "form": "fp64_words" if plan["form"] == 1 else "int8_digits", "tile": plan["tile"],
         },
         "roofline": roofline,

@@ -98,7 +98,19 @@ typedef struct {
                              product has too few output tiles for the chip
                              and a long k), 1 = never, > 1 = that many
                              k-ranges; their residues are added mod p */
-  int reserved[2];        /* must be zero */
+  int centered_words;     /* FP64 form, 1: centered words (project-derived
+                             variant of Alg. 4): each entry x is first mapped
+                             to x - p when 2x > p, then split with
+                             round-to-nearest quotients, so every word lies
+                             in [-alpha/2 - 1, alpha/2 + 1] and a word product
+                             is about a quarter of the paper's bound; the
+                             in-loop reduction rounds the quotient to nearest
+                             (c = floor(x q + 1/2)), leaving |x| <= p/2 + 4,
+                             and a block may hold L terms with
+                             p/2 + 4 + L W <= 2^t (W: the product of the two
+                             word bounds).  Exclusive with extended_block and
+                             strict_fmod.  0: the paper's words. */
+  int reserved[1];        /* must be zero */
 } mmp_opts;
 
 /* What the planner decided for one product (mmp_plan fills it). */
@@ -124,6 +136,8 @@ typedef struct {
   double est_seconds;     /* planner's cost-model estimate (0 if unknown) */
   int splits;             /* split-K k-ranges (1: none) */
   size_t workspace_bytes; /* device workspace the call needs */
+  int centered;           /* 1: centered words and the round-to-nearest
+                             in-loop reduction (mmp_opts.centered_words) */
 } mmp_plan_t;
 
 /* One product of a batch. */

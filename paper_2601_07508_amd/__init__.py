@@ -36,7 +36,7 @@ STATUS = {0: "MMP_OK", -1: "MMP_EINVAL", -2: "MMP_EBOUND", -3: "MMP_ERANGE", -4:
 class MmpOpts(ctypes.Structure):
     _fields_ = [("form", _int), ("validate_entries", _int), ("tile", _int), ("strict_fmod", _int),
                 ("force_kblock", _i64), ("workspace", _vp), ("workspace_bytes", _sz), ("extended_block", _int),
-                ("splits", _int), ("reserved", _int * 2)]
+                ("splits", _int), ("centered_words", _int), ("reserved", _int * 1)]
 
 
 class MmpPlan(ctypes.Structure):
@@ -45,7 +45,7 @@ class MmpPlan(ctypes.Structure):
                 ("tile", _int),
                 ("bm", _int), ("bn", _int), ("bk", _int), ("digits_a", _int), ("digits_b", _int),
                 ("kblock_int8", _i64), ("q", _dbl), ("est_seconds", _dbl), ("splits", _int),
-                ("workspace_bytes", _sz)]
+                ("workspace_bytes", _sz), ("centered", _int)]
 
     def as_dict(self):
         d = {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -143,10 +143,11 @@ def strerror(status: int) -> str:
 
 
 def _opts(form=FORM_AUTO, force_kblock=0, validate_entries=False, tile=0, strict_fmod=False,
-          workspace=None, extended_block=False, splits=0):
+          workspace=None, extended_block=False, splits=0, centered_words=False):
     o = MmpOpts()
     o.splits = splits
     o.extended_block = 1 if extended_block else 0
+    o.centered_words = 1 if centered_words else 0
     o.form = form
     o.force_kblock = force_kblock
     o.validate_entries = 1 if validate_entries else 0

@@ -36,7 +36,9 @@ constexpr int kPadB = 16;      // B plane rows: BN + 16 doubles (adjacent k-slot
 
 // ---- scalar modular arithmetic (binary64, explicit fma, no reassociation)
 
-// Alg. 1 without its two corrections, optionally biased by K p:
+// Alg. 1 without its two corrections, optionally biased by K p (with K = 1/2
+// the quotient is rounded to nearest and d lies within p/2 + 3 of zero, the
+// centered words' range):
 // c = floor(fl(x q + K)) is within one of floor(x / p) + K (the quotient
 // estimate of Prop. fpModularReductionFMA's proof, with the error of one
 // more rounding of a value below 2^(t+1) / p), so d = x - c p lies in
@@ -89,6 +91,22 @@ __device__ __forceinline__ void split_words(double x, double a, double ainv, dou
   w[W - 1] = t;
 }
 
+// Centered words (the library's variant of Alg. 4): x in [0, p) is first
+// taken to x - p when 2x > p, then split with quotients rounded to nearest,
+// so x - (0 or p) = sum_i a^i w[i] with |w[i]| <= a/2 + 1 below the top
+// word.  The words are congruent-preserving: the recombination is unchanged.
+template <int W>
+__device__ __forceinline__ void split_words_centered(double x, double p, double a, double ainv, double (&w)[W]) {
+  double t = (x + x > p) ? x - p : x;
+#pragma unroll
+  for (int i = 0; i < W - 1; i++) {
+    const double r = (ainv != 0.0) ? rint(t * ainv) : rint(t / a);
+    w[i] = fma(-a, r, t);
+    t = r;
+  }
+  w[W - 1] = t;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
 // that consecutive tile numbers run on the same XCD (shared L2), then walk
 // tiles in groups of 8 tile-rows so neighbours share A and B panels.
@@ -104,8 +122,24 @@ __device__ __forceinline__ void tile_coords(int bid, int nb, int nbm, int nbn, i
   tni = in / gm;
 }
 
+// s_waitcnt lgkmcnt(0) alone: this wave's LDS writes are complete, while its
+// global loads (vmcnt) may stay in flight across the barrier that follows.
+__device__ __forceinline__ void wait_lds_writes() {
+  __builtin_amdgcn_s_waitcnt(0xF | (0x3 << 14) | (0x7 << 4) | (0x0 << 8));
+}
+
+// Workgroup barrier that does not wait for outstanding global loads (the
+// compiler's __syncthreads would add vmcnt(0) and end the prefetch).  The
+// empty asm statements keep the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  wait_lds_writes();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int U, int V, int TM, int TN, int FE>
-__global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt) {
+__global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch bt) {
   static_assert(FE == 1 || FE == 2 || FE == 4, "reduction period");
   // which product of the batch this workgroup belongs to (uniform, scalar)
   int job = 0;
@@ -121,8 +155,10 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
   constexpr int LDB = BN + kPadB;
   constexpr int NA = (BM * kBK + kThreads - 1) / kThreads;  // A slab entries per thread (max)
   constexpr int NB = (kBK * BN + kThreads - 1) / kThreads;
-  __shared__ double As[U][BM][LDA];
-  __shared__ double Bs[V][kBK][LDB];
+  // two LDS stages: stage s is multiplied from buffer s & 1 while stage
+  // s + 1 is written into the other
+  __shared__ double As[2][U][BM][LDA];
+  __shared__ double Bs[2][V][kBK][LDB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -137,9 +173,9 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
   const int64_t m0 = (int64_t)tmi * BM;
   const int64_t n0 = (int64_t)tni * BN;
 
-  // zero both planes once: slots that no k-term maps to stay zero
-  for (int i = tid; i < U * BM * LDA; i += kThreads) (&As[0][0][0])[i] = 0.0;
-  for (int i = tid; i < V * kBK * LDB; i += kThreads) (&Bs[0][0][0])[i] = 0.0;
+  // zero both buffers once: slots that no k-term maps to stay zero
+  for (int i = tid; i < 2 * U * BM * LDA; i += kThreads) (&As[0][0][0][0])[i] = 0.0;
+  for (int i = tid; i < 2 * V * kBK * LDB; i += kThreads) (&Bs[0][0][0][0])[i] = 0.0;
 
   // Per-thread slab positions, fixed for every stage.  Real k-term kk of a
   // stage lands in slot (kk / L) S + kk % L when a block fits in a stage
@@ -178,15 +214,18 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
       rb[e] = (pos >= 0 && row < a.k && col < a.n) ? a.B[row * a.ldb + col] : 0.0;
     }
   };
-  auto store_stage = [&]() {
+  auto store_stage = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < NA; e++) {
       const int pos = a_pos[e];
       if (pos >= 0) {
         double w[U];
-        split_words<U>(ra[e], a.alpha, a.ainv, w);
+        if (a.centered)
+          split_words_centered<U>(ra[e], a.p, a.alpha, a.ainv, w);
+        else
+          split_words<U>(ra[e], a.alpha, a.ainv, w);
 #pragma unroll
-        for (int i = 0; i < U; i++) As[i][pos >> 16][pos & 0xff] = w[i];
+        for (int i = 0; i < U; i++) As[buf][i][pos >> 16][pos & 0xff] = w[i];
       }
     }
 #pragma unroll
@@ -194,9 +233,12 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
       const int pos = b_pos[e];
       if (pos >= 0) {
         double w[V];
-        split_words<V>(rb[e], a.beta, a.binv, w);
+        if (a.centered)
+          split_words_centered<V>(rb[e], a.p, a.beta, a.binv, w);
+        else
+          split_words<V>(rb[e], a.beta, a.binv, w);
 #pragma unroll
-        for (int j = 0; j < V; j++) Bs[j][pos & 0xff][(pos >> 8) & 0xff] = w[j];
+        for (int j = 0; j < V; j++) Bs[buf][j][pos & 0xff][(pos >> 8) & 0xff] = w[j];
       }
     }
   };
@@ -251,25 +293,31 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
     }
   };
 
+  // Stage s is split into buffer (s - s_begin) & 1 one iteration ahead; its
+  // global loads are issued one further iteration ahead, so they are in
+  // flight during a whole stage of MFMAs.  One barrier per stage: after it,
+  // every wave has finished reading the buffer the next store overwrites.
   int stage_in_block = 0;
-  if (s_begin < s_end) load_stage(s_begin * KR);
+  __syncthreads();  // the zeroed buffers are visible before any store
+  if (s_begin < s_end) {
+    load_stage(s_begin * KR);
+    store_stage(0);
+    if (s_begin + 1 < s_end) load_stage((s_begin + 1) * KR);
+  }
+  lds_barrier();
   for (int64_t s = s_begin; s < s_end; s++) {
-    __syncthreads();  // previous stage's MFMA reads are done
-    store_stage();
-    __syncthreads();
-    if (s + 1 < s_end) load_stage((s + 1) * KR);  // in flight during the MFMAs
-
+    const int buf = (int)((s - s_begin) & 1);
 #pragma unroll
     for (int ks = 0; ks < kBK / 4; ks++) {
       double af[U][TM], bf[V][TN];
 #pragma unroll
       for (int i = 0; i < U; i++)
 #pragma unroll
-        for (int x = 0; x < TM; x++) af[i][x] = As[i][wm + x * 16 + lrow][ks * 4 + lk];
+        for (int x = 0; x < TM; x++) af[i][x] = As[buf][i][wm + x * 16 + lrow][ks * 4 + lk];
 #pragma unroll
       for (int j = 0; j < V; j++)
 #pragma unroll
-        for (int y = 0; y < TN; y++) bf[j][y] = Bs[j][ks * 4 + lk][wn + y * 16 + lrow];
+        for (int y = 0; y < TN; y++) bf[j][y] = Bs[buf][j][ks * 4 + lk][wn + y * 16 + lrow];
 #pragma unroll
       for (int i = 0; i < U; i++)
 #pragma unroll
@@ -290,6 +338,11 @@ __global__ __launch_bounds__(kThreads) void fp64_words_kernel(const Fp64Batch bt
         reduce_all();
       }
     }
+    if (s + 1 < s_end) {
+      store_stage(buf ^ 1);
+      if (s + 2 < s_end) load_stage((s + 2) * KR);
+    }
+    lds_barrier();
   }
 
   // Epilogue: complete reduction and Horner recombination, then one store.

@@ -172,6 +172,12 @@ Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, c
     a.bias = (double)K;
     a.acc_init = -(double)(K * pl.p);
   }
+  if (pl.centered) {  // quotient rounded to nearest: c = floor(x q + 1/2)
+    a.centered = 1;
+    a.bias = 0.5;
+    a.acc_init = 0.0;
+    a.lazy = 1;
+  }
   return a;
 }
 

@@ -31,7 +31,7 @@ struct Fp64Tile {
 constexpr Fp64Tile fp64_tile_c(int tile_id, int uv) {
   return tile_id == 3   ? Fp64Tile{1, 1}
          : tile_id == 2 ? (uv <= 2 ? Fp64Tile{2, 2} : uv <= 4 ? Fp64Tile{1, 2} : Fp64Tile{1, 1})
-                        : (uv == 1   ? Fp64Tile{4, 4}
+                        : (uv == 1   ? Fp64Tile{4, 2}
                            : uv == 2 ? Fp64Tile{2, 4}
                            : uv <= 4 ? Fp64Tile{2, 2}
                                      : Fp64Tile{1, 2});
@@ -51,6 +51,12 @@ bool supported_words(int u, int v);
 // reduction's range) stays within [-2^t, 2^t].
 bool extended_block_ok(uint64_t p, int u, int v, int64_t L);
 int64_t extended_lambda(uint64_t p, int u, int v);
+// Centered words: largest |word| of an entry split into u words, and the
+// longest block whose partial sums stay within 2^t from the centered
+// reduction's range.
+uint64_t centered_word_bound(uint64_t p, int u);
+bool centered_block_ok(uint64_t p, int u, int v, int64_t L);
+int64_t centered_lambda(uint64_t p, int u, int v);
 
 int plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
          mmp_plan_t* out);
@@ -61,8 +67,8 @@ struct TunedChoice {
   int64_t kblock;
   double ms;
 };
-void tune_store(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, const TunedChoice& c);
-bool tune_lookup(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, TunedChoice* c);
+void tune_store(uint64_t p, int64_t m, int64_t n, int64_t k, int mode, const TunedChoice& c);
+bool tune_lookup(uint64_t p, int64_t m, int64_t n, int64_t k, int mode, TunedChoice* c);
 void tune_clear();
 int tune_save(const char* path);
 int tune_load(const char* path);
@@ -85,6 +91,7 @@ struct Fp64Args {
   double acc_init;       // accumulator start value: -K p (congruent to 0)
   int splits;            // split-K: k-ranges of this product (1: none)
   double* partial;       // splits > 1: residues per k-range, [splits][m][n]
+  int centered;          // centered words: x - p when 2x > p, round-to-nearest splits
 };
 
 // INT8-digit form: digit planes in a device workspace, then the digit GEMM.

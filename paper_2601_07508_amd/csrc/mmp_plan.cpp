@@ -74,6 +74,46 @@ int64_t extended_lambda(uint64_t p, int u, int v) {
   return (int64_t)lam;
 }
 
+// Centered words (a variant of Alg. 4 derived for this library).  An entry
+// x in [0, p) becomes x~ = x - p when 2x > p, so |x~| <= h = floor(p / 2),
+// and is split as x~ = sum_i alpha^i w_i with quotients rounded to nearest:
+// r = rint(t / alpha) (exact when alpha is a power of two, else a correctly
+// rounded division), w = t - r alpha.  Then |w| <= alpha / 2 + |t| 2^-53 <
+// alpha / 2 + 1 for every word but the last, and the last, the final
+// quotient, is at most h / alpha^(u-1) + 2.
+uint64_t centered_word_bound(uint64_t p, int u) {
+  const uint64_t h = p / 2;
+  if (u <= 1) return h;
+  const uint64_t a = iroot_ceil(p, u);
+  u128 apow = 1;
+  for (int i = 0; i < u - 1; i++) apow *= a;
+  const uint64_t top = (uint64_t)((u128)h / apow) + 2;
+  const uint64_t low = a / 2 + 1;
+  return top > low ? top : low;
+}
+
+// The centered in-loop reduction c = floor(fl(x q + 1/2)), d = x - c p maps
+// any |x| <= 2^t to |d| <= p/2 + 2.25 (the quotient estimate is within
+// 2/p + 2^-54 of x/p + 1/2); R = floor(p/2) + 4 bounds it with margin.  A
+// block of L terms, each of magnitude at most W = bound(u) bound(v), keeps
+// every partial sum within [-2^t, 2^t] if R + L W <= 2^t.
+static u128 centered_start(uint64_t p) { return (u128)(p / 2) + 4; }
+
+bool centered_block_ok(uint64_t p, int u, int v, int64_t L) {
+  const u128 w = (u128)centered_word_bound(p, u) * (u128)centered_word_bound(p, v);
+  return centered_start(p) + (u128)L * w <= (u128)kTwoT;
+}
+
+int64_t centered_lambda(uint64_t p, int u, int v) {
+  if (p < 5 || p >= kPMax) return 0;
+  const u128 w = (u128)centered_word_bound(p, u) * (u128)centered_word_bound(p, v);
+  const u128 start = centered_start(p);
+  if (start >= (u128)kTwoT || w == 0) return 0;
+  u128 lam = ((u128)kTwoT - start) / w;
+  if (lam > (u128)INT64_MAX) lam = INT64_MAX;
+  return (int64_t)lam;
+}
+
 bool lazy_block_ok(uint64_t p, int u, int v, int64_t L) {
   // A block starts from a value in [-p, 2p - 1] and adds L non-negative
   // terms, each at most w: every partial sum stays in [-p, 2^t] if
@@ -107,13 +147,15 @@ struct KBlock {
 // correction-free reduction where lazy_block_ok allows it.  With extended
 // allowed, blocks under the extended bound compete too (biased reduction);
 // near p = 2^(t-1) that bound is the smaller one and the paper mode wins.
-KBlock choose_kblock(uint64_t p, int u, int v, int64_t k, bool strict, bool allow_extended) {
+// Centered words: L <= centered_lambda, always the one-step reduction.
+KBlock choose_kblock(uint64_t p, int u, int v, int64_t k, bool strict, bool allow_extended,
+                     bool centered = false) {
   KBlock best{0, 0, false, false, 1e300};
-  const int64_t lam_paper = paper_lambda(p, u, v);
+  const int64_t lam_paper = centered ? centered_lambda(p, u, v) : paper_lambda(p, u, v);
   const int64_t lam_ext = allow_extended ? extended_lambda(p, u, v) : 0;
   auto consider = [&](int S, int64_t L, bool ext) {
     if (L < 1 || L > (ext ? lam_ext : lam_paper)) return;
-    const bool lazy = ext || (!strict && lazy_block_ok(p, u, v, L));
+    const bool lazy = centered || ext || (!strict && lazy_block_ok(p, u, v, L));
     double c = block_cost(S, L, lazy);
     // a block longer than k never reduces in the loop: cost of the MFMAs only
     if (L >= k && k > 0) c = 64.0 * (S / 4) / (double)L;
@@ -166,8 +208,9 @@ int pick_tile(int uv, int64_t m, int64_t n) {
 }
 
 // ---------------------------------------------------------------- tuning cache
-// Fastest measured plan per (bitsize of p, ceil(log2) of m, n, k, extended
-// allowed); filled by mmp_autotune, read by AUTO plans.
+// Fastest measured plan per (bitsize of p, ceil(log2) of m, n, k, bound mode:
+// 0 paper, 1 extended allowed, 2 centered words); filled by mmp_autotune,
+// read by AUTO plans.  The file field "ext" holds the mode.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, TunedChoice> g_tune;
 
@@ -179,20 +222,20 @@ int log2_ceil(int64_t x) {
 
 }  // namespace
 
-std::tuple<int, int, int, int, int> tune_key(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended) {
+std::tuple<int, int, int, int, int> tune_key(uint64_t p, int64_t m, int64_t n, int64_t k, int mode) {
   int bits = 0;
   while (bits < 64 && (p >> bits) != 0) bits++;
-  return std::make_tuple(bits, log2_ceil(m), log2_ceil(n), log2_ceil(k), extended ? 1 : 0);
+  return std::make_tuple(bits, log2_ceil(m), log2_ceil(n), log2_ceil(k), mode);
 }
 
-void tune_store(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, const TunedChoice& c) {
+void tune_store(uint64_t p, int64_t m, int64_t n, int64_t k, int mode, const TunedChoice& c) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[tune_key(p, m, n, k, extended)] = c;
+  g_tune[tune_key(p, m, n, k, mode)] = c;
 }
 
-bool tune_lookup(uint64_t p, int64_t m, int64_t n, int64_t k, bool extended, TunedChoice* c) {
+bool tune_lookup(uint64_t p, int64_t m, int64_t n, int64_t k, int mode, TunedChoice* c) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(tune_key(p, m, n, k, extended));
+  auto it = g_tune.find(tune_key(p, m, n, k, mode));
   if (it == g_tune.end()) return false;
   *c = it->second;
   return true;
@@ -283,8 +326,10 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
 
   const bool strict = o.strict_fmod != 0;
   const bool extended = o.extended_block != 0;
+  const bool centered = o.centered_words != 0;
   if (extended && strict) return MMP_EINVAL;  // the extended range needs the biased reduction
   if (extended && o.form == MMP_FORM_INT8_WORDS) return MMP_EINVAL;
+  if (centered && (extended || strict || o.form == MMP_FORM_INT8_WORDS)) return MMP_EINVAL;
 
   // INT8-digit form: asked for, or chosen by cost when neither the words
   // nor the block are forced.
@@ -325,7 +370,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   // A tuned choice for this class of products, if mmp_autotune measured one.
   if (use_tuned && o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0) {
     TunedChoice c;
-    if (tune_lookup(p, m, n, k, extended, &c)) {
+    if (tune_lookup(p, m, n, k, centered ? 2 : extended ? 1 : 0, &c)) {
       mmp_opts o2 = o;
       o2.form = c.form;
       o2.tile = c.form == MMP_FORM_FP64_WORDS ? c.tile : 0;
@@ -345,8 +390,8 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
       int cu = c[0], cv = c[1];
       if (n < m && cu > cv) continue;  // words on B when B is the narrower side
       if (n > m && cv > cu) continue;
-      if (paper_lambda(p, cu, cv) < 1) continue;
-      KBlock kb = choose_kblock(p, cu, cv, k, strict, extended);
+      if ((centered ? centered_lambda(p, cu, cv) : paper_lambda(p, cu, cv)) < 1) continue;
+      KBlock kb = choose_kblock(p, cu, cv, k, strict, extended, centered);
       double cost = kb.cost * cu * cv;
       if (cost < best * (1 - 1e-9)) {
         best = cost;
@@ -358,11 +403,14 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     if (best >= 1e299) return MMP_EBOUND;
   }
   const int64_t lambda = paper_lambda(p, bu, bv);
-  if (lambda < 1) return MMP_EBOUND;
+  const int64_t lam_c = centered ? centered_lambda(p, bu, bv) : 0;
+  if (centered ? lam_c < 1 : lambda < 1) return MMP_EBOUND;
   if (o.force_kblock > 0) {
     int64_t L = o.force_kblock;
-    // a forced block takes the paper's bound when it fits, else the extended one
-    const bool ext = L > lambda;
+    // a forced block takes the paper's bound when it fits, else the extended
+    // one; with centered words, the centered bound
+    const bool ext = !centered && L > lambda;
+    if (centered && L > lam_c) return MMP_EBOUND;
     if (ext && (!extended || L > extended_lambda(p, bu, bv))) return MMP_EBOUND;
     int S;
     if (L <= 4) S = 4;
@@ -371,9 +419,9 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     else if (L % kBK == 0) S = (int)std::min<int64_t>(L, (int64_t)1 << 26);
     else return MMP_EINVAL;  // longer blocks must be whole LDS stages
     if (L > ((int64_t)1 << 26)) return MMP_EINVAL;
-    bk = {L, S, ext || (!strict && lazy_block_ok(p, bu, bv, L)), ext, block_cost(S, L, false)};
+    bk = {L, S, centered || ext || (!strict && lazy_block_ok(p, bu, bv, L)), ext, block_cost(S, L, false)};
   } else if (u != 0) {
-    bk = choose_kblock(p, bu, bv, k, strict, extended);
+    bk = choose_kblock(p, bu, bv, k, strict, extended, centered);
   }
 
   out->p = p;
@@ -387,6 +435,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->slots = bk.S;
   out->lazy = bk.lazy ? 1 : 0;
   out->extended = bk.extended ? 1 : 0;
+  out->centered = centered ? 1 : 0;
   out->tile = o.tile ? o.tile : pick_tile(bu * bv, m, n);
   Fp64Tile t = fp64_tile(out->tile, bu * bv);
   out->bm = fp64_bm(t);
@@ -400,7 +449,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     out->splits = o.splits ? o.splits : choose_splits(tiles, cdiv(k, KR), 64);
     out->workspace_bytes = out->splits > 1 ? 8 * (size_t)out->splits * (size_t)m * (size_t)n : 0;
   }
-  if (o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0 && !extended &&
+  if (o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0 && !extended && !centered &&
       int8_seconds(m, n, k, d8) < out->est_seconds) {
     std::memset(out, 0, sizeof(*out));
     return plan_int8();

@@ -2,7 +2,8 @@
 // and caches the fastest for its class (bitsize of p; ceil(log2) of m, n, k).
 // Candidates: every word pair the paper's bound admits (Section 3.3) with
 // each tile shape and the planner's block for it (paper or, when allowed,
-// extended bound), and the INT8-digit form.
+// extended bound; with centered words, every pair the centered bound
+// admits), and the INT8-digit form unless a word-form option is set.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -31,6 +32,7 @@ int mmp_autotune(uint64_t p, int64_t m, int64_t n, int64_t k, const mmp_opts* op
     std::memset(&base, 0, sizeof(base));
     if (opts) base = *opts;
     const bool extended = base.extended_block != 0;
+    const bool centered = base.centered_words != 0;
     if (base.form != MMP_FORM_AUTO || base.force_kblock || base.tile) return MMP_EINVAL;
     mmp_plan_t probe;
     if (int st = plan(p, 0, 0, m, n, k, &base, &probe)) return st;  // validates p and sizes
@@ -40,7 +42,7 @@ int mmp_autotune(uint64_t p, int64_t m, int64_t n, int64_t k, const mmp_opts* op
     static const int pairs[][2] = {{1, 1}, {1, 2}, {2, 1}, {1, 3}, {3, 1}, {2, 2},
                                    {1, 4}, {4, 1}, {2, 3}, {3, 2}, {2, 4}, {4, 2}};
     for (auto& pr : pairs) {
-      if (paper_lambda(p, pr[0], pr[1]) < 1) continue;
+      if ((centered ? centered_lambda(p, pr[0], pr[1]) : paper_lambda(p, pr[0], pr[1])) < 1) continue;
       for (int tile = 1; tile <= 3; tile++) {
         mmp_opts o = base;
         o.form = MMP_FORM_FP64_WORDS;
@@ -50,7 +52,7 @@ int mmp_autotune(uint64_t p, int64_t m, int64_t n, int64_t k, const mmp_opts* op
           cands.push_back({MMP_FORM_FP64_WORDS, pr[0], pr[1], tile, pl.kblock});
       }
     }
-    if (!extended) cands.push_back({MMP_FORM_INT8_WORDS, 0, 0, 0, 0});
+    if (!extended && !centered) cands.push_back({MMP_FORM_INT8_WORDS, 0, 0, 0, 0});
 
     // scratch operands and output
     double *A = nullptr, *B = nullptr, *C = nullptr;
@@ -104,7 +106,7 @@ int mmp_autotune(uint64_t p, int64_t m, int64_t n, int64_t k, const mmp_opts* op
     (void)hipFree(A);
     if (err) return hip_status(err);
     if (win_ms >= 1e299) return MMP_EBOUND;
-    tune_store(p, m, n, k, extended, TunedChoice{win.form, win.u, win.v, win.tile, win.kblock, win_ms});
+    tune_store(p, m, n, k, centered ? 2 : extended ? 1 : 0, TunedChoice{win.form, win.u, win.v, win.tile, win.kblock, win_ms});
     return plan(p, 0, 0, m, n, k, &base, best);
   } catch (...) {
     return MMP_ENOMEM;

@@ -250,3 +250,91 @@ def test_split_k_fp64(splits):
         say("splitk fp64", p, u, v, splits)
         assert mmp.plan(p, m, n, k, u, v, splits=splits)["splits"] == splits
         assert_exact(run(p, A, B, u, v, splits=splits), oracle.mm_modp(p, A, B))
+
+
+# ------------------------------------------------------------------ centered words
+
+
+def _centered_worst(p, u):
+    h = p // 2
+    if u == 1:
+        return [h, p - h]
+    a = pa.iroot_ceil(p, u)
+    low = sum(a ** i * (a // 2 - 1) for i in range(u - 1))
+    x = (h - low) // a ** (u - 1) * a ** (u - 1) + low
+    return [x, p - x]
+
+
+@pytest.mark.parametrize("p", PRIMES + [134217689])
+def test_centered_parity_all_word_pairs(p):
+    ran = 0
+    for (u, v) in SUPPORTED:
+        try:
+            mmp.plan(p, 64, 64, 64, u, v, centered_words=True)
+        except mmp.MmpError:
+            continue
+        for (m, n, k) in [(17, 33, 29), (100, 70, 300), (130, 129, 67)]:
+            say("centered", p, u, v, m, n, k)
+            A = gen.random_matrix(p + m + 3, 1, m, k, p)
+            B = gen.random_matrix(p + n + 3, 2, k, n, p)
+            assert_exact(run(p, A, B, u, v, centered_words=True), oracle.mm_modp(p, A, B))
+            ran += 1
+    assert ran >= 1
+
+
+@pytest.mark.parametrize("p", [33554393, 67108859, 134217689, 2147483647, 68719476731,
+                               1125899906842597, 4503599627370449])
+def test_centered_worst_case(p):
+    # every word product of one sign, at its largest magnitude, over several
+    # full blocks; all four sign combinations of A and B
+    for (u, v) in SUPPORTED:
+        try:
+            pl = mmp.plan(p, 40, 36, 301, u, v, centered_words=True)
+        except mmp.MmpError:
+            continue
+        for x in _centered_worst(p, u):
+            for y in _centered_worst(p, v):
+                m, n, k = 40, 36, 301
+                A = np.full((m, k), x, dtype=np.uint64)
+                B = np.full((k, n), y, dtype=np.uint64)
+                say("centered worst", p, u, v, x, y, pl["kblock"])
+                assert_exact(run(p, A, B, u, v, centered_words=True), oracle.mm_modp(p, A, B))
+
+
+@pytest.mark.parametrize("p,u,v", [(33554393, 1, 1), (1125899906842597, 2, 2), (68719476731, 1, 3)])
+def test_centered_forced_kblock_up_to_bound(p, u, v):
+    m, n, k = 33, 47, 203
+    x, y = _centered_worst(p, u)[0], _centered_worst(p, v)[0]
+    A = np.full((m, k), x, dtype=np.uint64)
+    B = np.full((k, n), y, dtype=np.uint64)
+    want = oracle.mm_modp(p, A, B)
+    ok = 0
+    for L in list(range(1, 17)) + [32, 48, 64, 112]:
+        try:
+            mmp.plan(p, m, n, k, u, v, centered_words=True, force_kblock=L)
+        except mmp.MmpError:
+            continue
+        say("centered kblock", p, u, v, L)
+        assert_exact(run(p, A, B, u, v, centered_words=True, force_kblock=L), want)
+        ok += 1
+    assert ok >= 4
+
+
+def test_centered_equals_paper_words_large():
+    # one 50-bit (2,2) product at a size with many tiles and a ragged edge
+    p = 1125899906842597
+    m, n, k = 1000, 777, 1531
+    A = gen.random_matrix(5, 1, m, k, p)
+    B = gen.random_matrix(5, 2, k, n, p)
+    dA, dB = dev(A), dev(B)
+    C1 = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    C2 = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(dA, dB, C1, p, 2, 2, centered_words=True)
+    mmp.mm_modp_async(dA, dB, C2, p, 2, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    rr = np.arange(0, m, 37, dtype=np.int64)
+    cc = np.arange(0, n, 41, dtype=np.int64)
+    R, Cc = np.meshgrid(rr, cc, indexing="ij")
+    want = oracle.mm_modp_entries(p, A, B, R.ravel(), Cc.ravel()).astype(np.float64)
+    assert np.array_equal(C1.cpu().numpy()[R.ravel(), Cc.ravel()], want)

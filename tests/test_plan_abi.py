@@ -376,3 +376,153 @@ def test_tune_cache_entry_that_does_not_fit_is_ignored(tmp_path):
     assert not (pl["form"] == 1 and (pl["u"], pl["v"]) == (2, 2) and pl["kblock"] == 64)
     assert pl["form"] == 2 or pa.block_size(p, pl["u"], pl["v"]) >= pl["kblock"] or pl["extended"]
     mmp.tune_cache_clear()
+
+
+# ------------------------------------------------------------------ centered words
+# The opt-in centered words: x -> x - p when 2x > p, then a split with
+# quotients rounded to nearest (rint of a correctly rounded division), and
+# the in-loop reduction c = floor(fl(x q + 1/2)), d = x - c p.  Emulated
+# exactly in binary64 (Python floats are IEEE binary64 with round-to-nearest-
+# even; pa.fma rounds once).
+
+
+def _centered_words(x, p, a, u):
+    t = x - p if 2 * x > p else x
+    w = []
+    for _ in range(u - 1):
+        r = round(float(t) / float(a))  # rint: ties to even, as the kernel's rint
+        w.append(t - r * a)
+        t = r
+    w.append(t)
+    return w
+
+
+def _centered_word_bound(p, u):
+    # the library's bound, restated: floor(a/2) + 1 below the top word,
+    # floor(h / a^(u-1)) + 2 for the top word, h = floor(p/2) when u = 1
+    h = p // 2
+    if u == 1:
+        return h
+    a = pa.iroot_ceil(p, u)
+    return max(a // 2 + 1, h // a ** (u - 1) + 2)
+
+
+def _centered_reduce(x, p):
+    assert abs(x) <= TWO_T
+    b = pa.fma(float(x), 1.0 / p, 0.5)  # one rounding of x q + 1/2
+    d = x - math.floor(b) * p
+    assert abs(d) <= p // 2 + 3
+    return d
+
+
+def _emulate_centered(p, u, v, L, arow, bcol):
+    a_, b_ = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+    k = len(arow)
+    wa = [_centered_words(x, p, a_, u) for x in arow]
+    wb = [_centered_words(y, p, b_, v) for y in bcol]
+    peak = 0
+    out = [[0] * v for _ in range(u)]
+    for i in range(u):
+        for j in range(v):
+            s = 0
+            for l0 in range(0, k, L):
+                for l in range(l0, min(k, l0 + L)):
+                    s += wa[l][i] * wb[l][j]
+                    peak = max(peak, abs(s))
+                s = _centered_reduce(s, p)
+            out[i][j] = s % p
+    c = 0
+    for i in reversed(range(u)):
+        si = 0
+        for j in reversed(range(v)):
+            si = (si * b_ + out[i][j]) % p
+        c = (c * a_ + si) % p
+    return c, peak
+
+
+def centered_worst_entries(p, u):
+    """Entries whose centered words are all near their largest magnitude."""
+    h = p // 2
+    if u == 1:
+        return [h, p - h]
+    a = pa.iroot_ceil(p, u)
+    low = sum(a ** i * (a // 2 - 1) for i in range(u - 1))
+    top = (h - low) // a ** (u - 1)
+    x = top * a ** (u - 1) + low
+    assert 0 < x <= h
+    return [x, p - x, h, p - h]
+
+
+@pytest.mark.parametrize("p", [101, 1009, 65521, 100003])
+@pytest.mark.parametrize("u", [2, 3, 4])
+def test_centered_word_bound_brute_force(p, u):
+    # every entry of a small field: the words recombine to x or x - p and
+    # stay within the stated bound, which is reached up to its +1/+2 margin
+    a = pa.iroot_ceil(p, u)
+    bound = _centered_word_bound(p, u)
+    big = 0
+    for x in range(p):
+        w = _centered_words(x, p, a, u)
+        assert sum(a ** i * wi for i, wi in enumerate(w)) == (x - p if 2 * x > p else x)
+        assert all(abs(wi) <= a // 2 + 1 for wi in w[:-1])
+        assert abs(w[-1]) <= (p // 2) // a ** (u - 1) + 2
+        big = max(big, max(abs(wi) for wi in w))
+    assert bound - 2 <= big <= bound
+
+
+@pytest.mark.parametrize("p", [33554393, 67108859, 134217689, 2147483647, 68719476731, 1099511627689,
+                               1125899906842597, 4503599627370449])
+def test_centered_schedule_worst_case(p):
+    for (u, v) in SUPPORTED:
+        try:
+            pl = mmp.plan(p, 64, 64, 4096, u, v, centered_words=True)
+        except mmp.MmpError:
+            continue
+        L = pl["kblock"]
+        assert pl["centered"] == 1 and pl["lazy"] == 1 and pl["extended"] == 0
+        W = _centered_word_bound(p, u) * _centered_word_bound(p, v)
+        assert p // 2 + 4 + L * W <= TWO_T  # the centered bound
+        Lk = min(L, 40)
+        for x in centered_worst_entries(p, u):
+            for y in centered_worst_entries(p, v):
+                k = 2 * Lk + 3
+                c, peak = _emulate_centered(p, u, v, Lk, [x] * k, [y] * k)
+                assert c == (k * x * y) % p
+                assert peak <= TWO_T
+
+
+def test_centered_longest_block_is_the_bound():
+    # the planner's block never exceeds the bound, and one more term would
+    for p in [33554393, 1125899906842597, 68719476731]:
+        for (u, v) in [(1, 1), (2, 2), (1, 3)]:
+            W = _centered_word_bound(p, u) * _centered_word_bound(p, v)
+            lam = (TWO_T - p // 2 - 4) // W
+            if lam < 1:
+                with pytest.raises(mmp.MmpError):
+                    mmp.plan(p, 64, 64, 64, u, v, centered_words=True)
+                continue
+            L = min(lam, 1 << 20)
+            if L > 16:
+                L = L // 16 * 16
+            mmp.plan(p, 64, 64, 64, u, v, centered_words=True, force_kblock=L)
+            if lam <= 16:
+                with pytest.raises(mmp.MmpError):
+                    mmp.plan(p, 64, 64, 64, u, v, centered_words=True, force_kblock=lam + 1)
+
+
+def test_centered_quadruples_block_at_50_bits():
+    p = 1125899906842597
+    pl = mmp.plan(p, 8192, 8192, 8192, 2, 2, centered_words=True)
+    assert (pl["kblock"], pl["slots"], pl["centered"]) == (16, 16, 1)  # 29 allowed, one LDS stage
+    assert mmp.plan(p, 8192, 8192, 8192, 2, 2)["kblock"] == 4
+    # centered words reach one bit past the paper's (1,1) limit of 26 bits
+    p27 = gen.prev_prime(1 << 27)
+    assert pa.block_size(p27, 1, 1) < 1
+    assert mmp.plan(p27, 64, 64, 64, 1, 1, centered_words=True)["kblock"] >= 1
+
+
+@pytest.mark.parametrize("bad", [dict(extended_block=True), dict(strict_fmod=True), dict(form=2)])
+def test_centered_option_conflicts(bad):
+    with pytest.raises(mmp.MmpError):
+        mmp.plan(1125899906842597, 64, 64, 64, 0 if bad.get("form") else 2, 0 if bad.get("form") else 2,
+                 centered_words=True, **bad)
