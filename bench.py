@@ -32,16 +32,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_digest():
+# The sources that define each form's dominant kernel and its launch: a
+# counter record taken on other sources than these is stale.
+KERNEL_SOURCES = {
+    1: ["fp64_words_kernel.h", "mmp_fp64_words.hip"],
+    2: ["int8_digits_kernel.h", "mmp_int8_digits.hip"],
+}
+
+
+def source_digest(form):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2601_07508_amd", "csrc")
-    for fn in sorted(os.listdir(d)):
+    for fn in KERNEL_SOURCES[form]:
         with open(os.path.join(d, fn), "rb") as f:
             h.update(fn.encode() + f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(workload, digest):
+def traffic_for(workload, kernel, digest):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
     were taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -51,7 +59,7 @@ def traffic_for(workload, digest):
         rec = json.load(open(path)).get(workload)
     except Exception:
         return None
-    if not rec or rec.get("source_digest") != digest:
+    if not rec or rec.get("source_digest") != digest or not rec.get("kernel", "").startswith(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -360,7 +368,7 @@ def main():
 
     mnk = float(prob.m) * prob.n * prob.k
     eff = 2.0 * mnk / (ms * 1e-3) / 1e9
-    digest = source_digest()
+    digest = source_digest(plan["form"])
     workload = prob.tag
     if plan["form"] == 1:
         kernel, phase, peak, unit = "fp64_words_kernel", "fp64_words", FP64_MFMA_PEAK_TFLOPS, "TFLOP/s"
@@ -377,7 +385,7 @@ def main():
         "peak": peak,
         "unit": unit,
         "frac": round(achieved / peak, 4),
-        "traffic": traffic_for(workload, digest),
+        "traffic": traffic_for(workload, kernel, digest),
         "kernel": kernel,
         "kernel_ms": round(kern_ms, 4),
         "algorithmic_work_per_launch": work,

@@ -102,8 +102,8 @@ typedef struct {
                              variant of Alg. 4): each entry x is first mapped
                              to x - p when 2x > p, then split with
                              round-to-nearest quotients, so every word lies
-                             in [-alpha/2 - 1, alpha/2 + 1] and a word product
-                             is about a quarter of the paper's bound; the
+                             within alpha/2 + 2 of zero and a word product is
+                             about a quarter of the paper's bound; the
                              in-loop reduction rounds the quotient to nearest
                              (c = floor(x q + 1/2)), leaving |x| <= p/2 + 4,
                              and a block may hold L terms with

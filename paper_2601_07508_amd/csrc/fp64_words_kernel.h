@@ -32,7 +32,17 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;  // 4 waves of 64
 constexpr int kPadA = 1;       // A plane rows: kBK + 1 doubles (16 rows hit distinct banks)
-constexpr int kPadB = 16;      // B plane rows: BN + 16 doubles (adjacent k-slots 32 banks apart)
+// B plane rows hold BN doubles with no padding; odd k-slots store column c
+// at c ^ 16, so the two k-slots one half-wave reads sit 32 banks apart.
+__device__ __forceinline__ int bswz(int slot, int c) { return c ^ ((slot & 1) << 4); }
+
+// Raw buffer loads (dword 3 of the resource for the gfx9 family): reads at or
+// past the resource's byte count return zero instead of touching memory.
+constexpr int kBufferWord3 = 0x00020000;
+__device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  typedef int v2i __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
 
 // ---- scalar modular arithmetic (binary64, explicit fma, no reassociation)
 
@@ -76,32 +86,34 @@ __device__ __forceinline__ double addmod(double x, double y, double p) {
   return (s >= p) ? s - p : s;
 }
 
-// Alg. 4 on one entry: words w[0..W-1] with x = sum_i a^i w[i], 0 <= w[i] < a.
-// The quotient is floor(T / a) with a correctly rounded division (Lemma
-// exactFpDiv); when a is a power of two, T * (1/a) is the same exact value.
+// Alg. 4 on one entry, with the library's centered variant.
+//   paper words (rbias = 0): x = sum_i a^i w[i] with 0 <= w[i] < a; each
+//     quotient is floor(t / a): r = floor(fl(t ainv)) with ainv = fl(1/a) is
+//     exact when a is a power of two and otherwise within one of the
+//     quotient (t < 2^53), so one correction step in each direction makes it
+//     exact (fix = 1);
+//   centered words (cen = 1, rbias = 1/2): x is first taken to x - p when
+//     2x > p, and r = floor(fl(t ainv + 1/2)) rounds to nearest within
+//     |t| 2^-52 < 1/2, so |w[i]| < a/2 + 1 below the top word with no
+//     correction; x - (0 or p) = sum_i a^i w[i] exactly either way.
+// Branch-free: cen and fix are uniform over the launch.
 template <int W>
-__device__ __forceinline__ void split_words(double x, double a, double ainv, double (&w)[W]) {
-  double t = x;
+__device__ __forceinline__ void split_entry(double x, double p, double a, double ainv, double rbias, bool cen,
+                                            bool fix, double (&w)[W]) {
+  double t = (cen && x + x > p) ? x - p : x;
 #pragma unroll
   for (int i = 0; i < W - 1; i++) {
-    const double r = (ainv != 0.0) ? floor(t * ainv) : floor(t / a);
-    w[i] = fma(-a, r, t);
-    t = r;
-  }
-  w[W - 1] = t;
-}
-
-// Centered words (the library's variant of Alg. 4): x in [0, p) is first
-// taken to x - p when 2x > p, then split with quotients rounded to nearest,
-// so x - (0 or p) = sum_i a^i w[i] with |w[i]| <= a/2 + 1 below the top
-// word.  The words are congruent-preserving: the recombination is unchanged.
-template <int W>
-__device__ __forceinline__ void split_words_centered(double x, double p, double a, double ainv, double (&w)[W]) {
-  double t = (x + x > p) ? x - p : x;
-#pragma unroll
-  for (int i = 0; i < W - 1; i++) {
-    const double r = (ainv != 0.0) ? rint(t * ainv) : rint(t / a);
-    w[i] = fma(-a, r, t);
+    double r = floor(fma(t, ainv, rbias));
+    double d = fma(-a, r, t);
+    if (fix) {
+      const bool lo = d < 0.0;
+      r = lo ? r - 1.0 : r;
+      d = lo ? d + a : d;
+      const bool hi = d >= a;
+      r = hi ? r + 1.0 : r;
+      d = hi ? d - a : d;
+    }
+    w[i] = d;
     t = r;
   }
   w[W - 1] = t;
@@ -138,7 +150,7 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
-template <int U, int V, int TM, int TN, int FE>
+template <int U, int V, int TM, int TN, int FE, bool PAD>
 __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch bt) {
   static_assert(FE == 1 || FE == 2 || FE == 4, "reduction period");
   // which product of the batch this workgroup belongs to (uniform, scalar)
@@ -152,9 +164,10 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
   constexpr int BM = 2 * TM * 16;
   constexpr int BN = 2 * TN * 16;
   constexpr int LDA = kBK + kPadA;
-  constexpr int LDB = BN + kPadB;
-  constexpr int NA = (BM * kBK + kThreads - 1) / kThreads;  // A slab entries per thread (max)
-  constexpr int NB = (kBK * BN + kThreads - 1) / kThreads;
+  constexpr int LDB = BN;
+  constexpr int NA = BM * kBK / kThreads;  // A slab entries per thread
+  constexpr int NB = kBK * BN / kThreads;
+  static_assert(NA * kThreads == BM * kBK && NB * kThreads == kBK * BN, "whole slabs per thread");
   // two LDS stages: stage s is multiplied from buffer s & 1 while stage
   // s + 1 is written into the other
   __shared__ double As[2][U][BM][LDA];
@@ -177,69 +190,103 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
   for (int i = tid; i < 2 * U * BM * LDA; i += kThreads) (&As[0][0][0][0])[i] = 0.0;
   for (int i = tid; i < 2 * V * kBK * LDB; i += kThreads) (&Bs[0][0][0][0])[i] = 0.0;
 
-  // Per-thread slab positions, fixed for every stage.  Real k-term kk of a
-  // stage lands in slot (kk / L) S + kk % L when a block fits in a stage
-  // (S <= kBK, the remaining S - L slots of each block stay zero), else in
-  // slot kk (blocks span whole stages, L = S).
+  // Slab elements.  Each stage reads an A slab (BM rows x KR k-terms) and a
+  // B slab (KR x BN) with buffer loads: per-stage resources start at
+  // (m0, k0) of A and (k0, n0) of B and end at the last entry of the
+  // matrix, so rows of A past m and rows of B past k read as zero (the
+  // first only feed outputs that are never stored); columns of A past k are
+  // zeroed explicitly in the last stage.  Per-thread byte offsets into the
+  // slab stay fixed across stages.
+  //   whole stages (PAD = false, KR = 16): thread t takes k-term t % 16 of A
+  //     rows t / 16 + 16 e, and column t % BN of B k-rows t / BN + (256/BN) e,
+  //     so its LDS destinations are affine in e;
+  //   padded stages (PAD, KR < 16 real terms in 16 slots): real term kk goes
+  //     to slot (kk / L) S + kk % L and the other slots keep their zeros;
+  //     elements past the slab are idle: zero values written to A's pad
+  //     column (never read) and to B's slot L (a zero slot when L < S).
   const int KR = a.KR;
-  // packed positions: A: row << 16 | kk << 8 | slot;  B: kk << 16 | col << 8 | slot;  -1: idle
-  int a_pos[NA], b_pos[NB];
+  constexpr int AROWS = kThreads / kBK;  // A rows between a thread's elements
+  constexpr int BROWS = kThreads / BN;   // B k-rows between a thread's elements
+  uint32_t a_off[NA], b_off[NB];
+  int a_meta[PAD ? NA : 1], b_meta[PAD ? NB : 1];  // LDS element offset | kk << 16
+  int a_dst0 = 0, b_dst0 = 0, t_kk = 0;
+  if constexpr (!PAD) {
+    const int r0 = tid / kBK, c0 = tid % BN, kb = tid / BN;
+    t_kk = tid % kBK;
 #pragma unroll
-  for (int e = 0; e < NA; e++) {
-    const int idx = tid + e * kThreads;
-    const int r = idx / KR, kk = idx - r * KR;
-    const int slot = (a.S <= kBK) ? (kk / a.L) * a.S + kk % a.L : kk;
-    a_pos[e] = (idx < BM * KR) ? ((r << 16) | (kk << 8) | slot) : -1;
-  }
+    for (int e = 0; e < NA; e++) a_off[e] = (uint32_t)(((int64_t)(r0 + AROWS * e) * a.lda + t_kk) * 8);
 #pragma unroll
-  for (int e = 0; e < NB; e++) {
-    const int idx = tid + e * kThreads;
-    const int kk = idx / BN, c = idx % BN;
-    const int slot = (a.S <= kBK) ? (kk / a.L) * a.S + kk % a.L : kk;
-    b_pos[e] = (idx < KR * BN) ? ((kk << 16) | (c << 8) | slot) : -1;
-  }
-
-  double ra[NA], rb[NB];
-  auto load_stage = [&](int64_t k0) {
+    for (int e = 0; e < NB; e++) b_off[e] = (uint32_t)(((int64_t)(kb + BROWS * e) * a.ldb + c0) * 8);
+    a_dst0 = r0 * LDA + t_kk;
+    b_dst0 = kb * LDB + bswz(kb, c0);  // BROWS is even: every element has kb's parity
+  } else {
 #pragma unroll
     for (int e = 0; e < NA; e++) {
-      const int pos = a_pos[e];
-      const int64_t row = m0 + (pos >> 16), col = k0 + ((pos >> 8) & 0xff);
-      ra[e] = (pos >= 0 && row < a.m && col < a.k) ? a.A[row * a.lda + col] : 0.0;
+      const int idx = tid + e * kThreads;
+      const bool valid = idx < BM * KR;
+      const int r = valid ? idx / KR : 0, kk = valid ? idx % KR : 0;
+      const int slot = (kk / a.L) * a.S + kk % a.L;
+      a_off[e] = (uint32_t)(((int64_t)r * a.lda + kk) * 8);
+      a_meta[e] = valid ? (r * LDA + slot) | (kk << 16) : kBK | (kBK << 16);
     }
 #pragma unroll
     for (int e = 0; e < NB; e++) {
-      const int pos = b_pos[e];
-      const int64_t row = k0 + (pos >> 16), col = n0 + ((pos >> 8) & 0xff);
-      rb[e] = (pos >= 0 && row < a.k && col < a.n) ? a.B[row * a.ldb + col] : 0.0;
+      const int idx = tid + e * kThreads;
+      const bool valid = idx < KR * BN;
+      const int kk = valid ? idx / BN : 0, c = valid ? idx % BN : 0;
+      const int slot = (kk / a.L) * a.S + kk % a.L;
+      b_off[e] = (uint32_t)(((int64_t)kk * a.ldb + c) * 8);
+      b_meta[e] = valid ? (slot * LDB + bswz(slot, c)) | (kk << 16) : (a.L * LDB + bswz(a.L, 0)) | (kBK << 16);
+    }
+  }
+  const double p = a.p, q = a.q, bias = a.bias;
+  const bool cen = a.centered != 0;
+  const double rbias = cen ? 0.5 : 0.0;
+  const bool afix = !cen && a.afix, bfix = !cen && a.bfix;
+
+  double ra[NA], rb[NB];
+  auto load_stage = [&](int64_t k0) {
+    const int64_t left = a.k - k0;  // real k-terms from k0 on (>= 1)
+    const int64_t abytes = ((a.m - m0 - 1) * a.lda + left) * 8;
+    const int64_t bbytes = ((left - 1) * a.ldb + (a.n - n0)) * 8;
+    const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.A + m0 * a.lda + k0), (short)0, (int)(abytes < 0x7fffffff ? abytes : 0x7fffffff), kBufferWord3);
+    const __amdgpu_buffer_rsrc_t br = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.B + k0 * a.ldb + n0), (short)0, (int)(bbytes < 0x7fffffff ? bbytes : 0x7fffffff), kBufferWord3);
+#pragma unroll
+    for (int e = 0; e < NA; e++) ra[e] = buffer_load_f64(ar, a_off[e]);
+#pragma unroll
+    for (int e = 0; e < NB; e++) rb[e] = buffer_load_f64(br, b_off[e]);
+    if constexpr (!PAD) {
+      if (left < kBK) {  // the k tail: A's columns past k hold other data
+        const bool ok = t_kk < left;
+#pragma unroll
+        for (int e = 0; e < NA; e++) ra[e] = ok ? ra[e] : 0.0;
+      }
+    } else {
+      const int lim = (int)(left < KR ? left : KR);
+#pragma unroll
+      for (int e = 0; e < NA; e++) ra[e] = (a_meta[e] >> 16) < lim ? ra[e] : 0.0;
+#pragma unroll
+      for (int e = 0; e < NB; e++) rb[e] = (b_meta[e] >> 16) < lim ? rb[e] : 0.0;
     }
   };
   auto store_stage = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < NA; e++) {
-      const int pos = a_pos[e];
-      if (pos >= 0) {
-        double w[U];
-        if (a.centered)
-          split_words_centered<U>(ra[e], a.p, a.alpha, a.ainv, w);
-        else
-          split_words<U>(ra[e], a.alpha, a.ainv, w);
+      double w[U];
+      split_entry<U>(ra[e], p, a.alpha, a.ainv, rbias, cen, afix, w);
+      const int dst = PAD ? (a_meta[PAD ? e : 0] & 0xffff) : a_dst0 + e * AROWS * LDA;
 #pragma unroll
-        for (int i = 0; i < U; i++) As[buf][i][pos >> 16][pos & 0xff] = w[i];
-      }
+      for (int i = 0; i < U; i++) (&As[buf][i][0][0])[dst] = w[i];
     }
 #pragma unroll
     for (int e = 0; e < NB; e++) {
-      const int pos = b_pos[e];
-      if (pos >= 0) {
-        double w[V];
-        if (a.centered)
-          split_words_centered<V>(rb[e], a.p, a.beta, a.binv, w);
-        else
-          split_words<V>(rb[e], a.beta, a.binv, w);
+      double w[V];
+      split_entry<V>(rb[e], p, a.beta, a.binv, rbias, cen, bfix, w);
+      const int dst = PAD ? (b_meta[PAD ? e : 0] & 0xffff) : b_dst0 + e * BROWS * LDB;
 #pragma unroll
-        for (int j = 0; j < V; j++) Bs[buf][j][pos & 0xff][(pos >> 8) & 0xff] = w[j];
-      }
+      for (int j = 0; j < V; j++) (&Bs[buf][j][0][0])[dst] = w[j];
     }
   };
 
@@ -253,7 +300,6 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
 #pragma unroll
         for (int y = 0; y < TN; y++) acc[i][j][x][y] = (d4){a.acc_init, a.acc_init, a.acc_init, a.acc_init};
 
-  const double p = a.p, q = a.q, bias = a.bias;
   const int64_t nstages_all = (a.k + KR - 1) / KR;
   // this split's stages: [s_begin, s_end)
   const int64_t per_split = (nstages_all + a.splits - 1) / a.splits;
@@ -317,7 +363,7 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
 #pragma unroll
       for (int j = 0; j < V; j++)
 #pragma unroll
-        for (int y = 0; y < TN; y++) bf[j][y] = Bs[buf][j][ks * 4 + lk][wn + y * 16 + lrow];
+        for (int y = 0; y < TN; y++) bf[j][y] = Bs[buf][j][ks * 4 + lk][bswz(lk, wn + y * 16 + lrow)];
 #pragma unroll
       for (int i = 0; i < U; i++)
 #pragma unroll
@@ -376,10 +422,10 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
 }
 
 // The tile shapes of fp64_tile_c() as compile-time constants.
-template <int UV, int ID>
+template <int U, int V, int ID>
 struct TileOf {
-  static constexpr int tm = fp64_tile_c(ID, UV).tm;
-  static constexpr int tn = fp64_tile_c(ID, UV).tn;
+  static constexpr int tm = fp64_tile_c(ID, U, V).tm;
+  static constexpr int tn = fp64_tile_c(ID, U, V).tn;
 };
 
 // Tiles of one product for a given shape.
@@ -388,13 +434,17 @@ inline int64_t tiles_of(const Fp64Args& a) {
   return ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN) * a.splits;
 }
 
-template <int U, int V, int ID, int FE>
+template <int U, int V, int ID, int FE, bool PAD>
 int launch_shape(const Fp64Batch& b0, hipStream_t s) {
-  constexpr int TM = TileOf<U * V, ID>::tm, TN = TileOf<U * V, ID>::tn;
+  constexpr int TM = TileOf<U, V, ID>::tm, TN = TileOf<U, V, ID>::tn;
   constexpr int BM = 2 * 16 * TM, BN = 2 * 16 * TN;
   Fp64Batch b = b0;
   int64_t total = 0;
   for (int j = 0; j < b.njobs; j++) {
+    // the kernel's 32-bit slab offsets: BM rows of A and 16 k-rows of B
+    const Fp64Args& x = b.job[j];
+    if (((BM - 1) * x.lda + kBK) * 8 >= ((int64_t)1 << 31) || (kBK * x.ldb + BN) * 8 >= ((int64_t)1 << 31))
+      return (int)hipErrorInvalidValue;
     b.tile_start[j] = (int)total;
     total += tiles_of<BM, BN>(b.job[j]);
     if (total > 0x7fffffff) return (int)hipErrorInvalidValue;
@@ -402,7 +452,7 @@ int launch_shape(const Fp64Batch& b0, hipStream_t s) {
   b.tile_start[b.njobs] = (int)total;
   if (total <= 0) return 0;
   TimerTok* t = timer_begin("fp64_words");
-  hipExtLaunchKernelGGL((fp64_words_kernel<U, V, TM, TN, FE>), dim3((unsigned)total), dim3(kThreads), 0, s,
+  hipExtLaunchKernelGGL((fp64_words_kernel<U, V, TM, TN, FE, PAD>), dim3((unsigned)total), dim3(kThreads), 0, s,
                         timer_start(t), timer_stop(t), 0, b);
   const int e = (int)hipGetLastError();
   timer_commit(t, e);

@@ -159,8 +159,10 @@ Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, c
   a.q = pl.q;
   a.alpha = (double)pl.alpha;
   a.beta = (double)pl.beta;
-  a.ainv = (pl.u > 1 && is_pow2(pl.alpha)) ? 1.0 / (double)pl.alpha : 0.0;
-  a.binv = (pl.v > 1 && is_pow2(pl.beta)) ? 1.0 / (double)pl.beta : 0.0;
+  a.ainv = 1.0 / (double)pl.alpha;
+  a.binv = 1.0 / (double)pl.beta;
+  a.afix = (pl.u > 1 && !is_pow2(pl.alpha)) ? 1 : 0;
+  a.bfix = (pl.v > 1 && !is_pow2(pl.beta)) ? 1 : 0;
   a.L = (int)pl.kblock;
   a.S = pl.slots;
   a.KR = (pl.slots <= kBK) ? (kBK / pl.slots) * (int)pl.kblock : kBK;

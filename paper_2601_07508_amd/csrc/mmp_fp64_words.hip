@@ -18,13 +18,19 @@ int MMP_CAT(launch_fp64_words_, MMP_U, MMP_V)(int tile_id, const Fp64Batch& a, v
   hipStream_t s = (hipStream_t)stream;
   (void)UV;
   // k-steps per in-loop reduction: S / 4 for S in {4, 8}, else 4 (whole
-  // stages); every product of a batch has the same period
-  const int fe = a.job[0].S == 4 ? 1 : a.job[0].S == 8 ? 2 : 4;
-#define MMP_SHAPE(ID_)                                                  \
-  if (tile_id == ID_) {                                                 \
-    if (fe == 1) return launch_shape<MMP_U, MMP_V, ID_, 1>(a, s);       \
-    if (fe == 2) return launch_shape<MMP_U, MMP_V, ID_, 2>(a, s);       \
-    return launch_shape<MMP_U, MMP_V, ID_, 4>(a, s);                    \
+  // stages); padded stages when a block leaves zero slots (L < S <= 16);
+  // every product of a batch has the same class (fp64_class)
+  const int cls = fp64_class(a.job[0].S, a.job[0].L);
+  const int fe = cls >> 1;
+  const bool pad = (cls & 1) != 0;
+#define MMP_SHAPE(ID_)                                                                  \
+  if (tile_id == ID_) {                                                                 \
+    if (fe == 1) return pad ? launch_shape<MMP_U, MMP_V, ID_, 1, true>(a, s)            \
+                            : launch_shape<MMP_U, MMP_V, ID_, 1, false>(a, s);          \
+    if (fe == 2) return pad ? launch_shape<MMP_U, MMP_V, ID_, 2, true>(a, s)            \
+                            : launch_shape<MMP_U, MMP_V, ID_, 2, false>(a, s);          \
+    return pad ? launch_shape<MMP_U, MMP_V, ID_, 4, true>(a, s)                         \
+               : launch_shape<MMP_U, MMP_V, ID_, 4, false>(a, s);                       \
   }
   MMP_SHAPE(1)
   MMP_SHAPE(2)

@@ -28,15 +28,20 @@ struct Fp64Tile {
 // tile id 1 (large), 2 (medium), 3 (small) for a given number of word products.
 // Accumulator VGPRs per lane = uv * tm * tn * 8 (a 16x16 FP64 tile is 4
 // values of 2 VGPRs per lane); the shapes keep that at 96..128.
-constexpr Fp64Tile fp64_tile_c(int tile_id, int uv) {
-  return tile_id == 3   ? Fp64Tile{1, 1}
-         : tile_id == 2 ? (uv <= 2 ? Fp64Tile{2, 2} : uv <= 4 ? Fp64Tile{1, 2} : Fp64Tile{1, 1})
-                        : (uv == 1   ? Fp64Tile{4, 2}
-                           : uv == 2 ? Fp64Tile{2, 4}
-                           : uv <= 4 ? Fp64Tile{2, 2}
-                                     : Fp64Tile{1, 2});
+// Tile 1, the large shape, keeps each word pair within 256 VGPRs and two
+// workgroups per CU (LDS): the longer side goes to the operand with fewer
+// words, whose fragments are the cheaper ones to hold.
+constexpr Fp64Tile fp64_tile_c(int tile_id, int u, int v) {
+  if (tile_id == 3) return Fp64Tile{1, 1};
+  if (tile_id == 2) return u * v <= 2 ? Fp64Tile{2, 2} : u * v <= 4 ? Fp64Tile{1, 2} : Fp64Tile{1, 1};
+  if (u == 1 && v == 1) return Fp64Tile{4, 2};
+  if (u * v == 2) return u < v ? Fp64Tile{4, 2} : Fp64Tile{2, 4};
+  if (u == 1 && v == 4) return Fp64Tile{4, 1};
+  if (u == 4 && v == 1) return Fp64Tile{1, 4};
+  if (u * v <= 4) return Fp64Tile{2, 2};  // (1,3), (3,1), (2,2)
+  return u >= v ? Fp64Tile{1, 2} : Fp64Tile{2, 1};
 }
-inline Fp64Tile fp64_tile(int tile_id, int uv) { return fp64_tile_c(tile_id, uv); }
+inline Fp64Tile fp64_tile(int tile_id, int u, int v) { return fp64_tile_c(tile_id, u, v); }
 inline int fp64_bm(const Fp64Tile& t) { return 2 * 16 * t.tm; }
 inline int fp64_bn(const Fp64Tile& t) { return 2 * 16 * t.tn; }
 
@@ -81,7 +86,8 @@ struct Fp64Args {
   const double* B;
   double* C;
   int64_t m, n, k, lda, ldb, ldc;
-  double p, q, alpha, beta, ainv, binv;  // ainv/binv: exact 1/alpha, 1/beta when powers of two, else 0
+  double p, q, alpha, beta, ainv, binv;  // ainv, binv: fl(1/alpha), fl(1/beta)
+  int afix, bfix;        // 1: the base is not a power of two, so a split quotient needs its correction step
   int L;           // real k-terms per block
   int S;           // k-slots per block (S >= L; zeros fill the rest)
   int KR;          // real k-terms per LDS stage
@@ -165,8 +171,14 @@ struct Fp64Batch {
   int tile_start[kMaxBatch + 1];  // filled by the launcher
   Fp64Args job[kMaxBatch];
 };
-// k-steps per in-loop reduction class of a plan: jobs of one launch share it
-inline int fp64_fe(int slots) { return slots == 4 ? 1 : slots == 8 ? 2 : 4; }
+// Kernel class of a plan, 2 FE + PAD: FE = k-steps per in-loop reduction
+// (1, 2 or 4), PAD = blocks leave zero slots in a stage (L < S <= 16).
+// Jobs of one launch share it.
+inline int fp64_class(int slots, int64_t kblock) {
+  const int fe = slots == 4 ? 1 : slots == 8 ? 2 : 4;
+  const int pad = (slots <= kBK && kblock < slots) ? 1 : 0;
+  return 2 * fe + pad;
+}
 
 // Launch the fused FP64-word kernel; returns a hipError_t value (0 = success).
 int launch_fp64_words(int u, int v, int tile_id, const Fp64Batch& a, void* stream);

@@ -198,9 +198,9 @@ double int8_seconds(int64_t m, int64_t n, int64_t k, int d) {
   return gemm + digitize + fold + 3 * 4e-6;
 }
 
-int pick_tile(int uv, int64_t m, int64_t n) {
+int pick_tile(int u, int v, int64_t m, int64_t n) {
   for (int id = 1; id <= 3; id++) {
-    Fp64Tile t = fp64_tile(id, uv);
+    Fp64Tile t = fp64_tile(id, u, v);
     int64_t nb = cdiv(m, fp64_bm(t)) * cdiv(n, fp64_bn(t));
     if (nb >= 512) return id;
   }
@@ -436,8 +436,8 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->lazy = bk.lazy ? 1 : 0;
   out->extended = bk.extended ? 1 : 0;
   out->centered = centered ? 1 : 0;
-  out->tile = o.tile ? o.tile : pick_tile(bu * bv, m, n);
-  Fp64Tile t = fp64_tile(out->tile, bu * bv);
+  out->tile = o.tile ? o.tile : pick_tile(bu, bv, m, n);
+  Fp64Tile t = fp64_tile(out->tile, bu, bv);
   out->bm = fp64_bm(t);
   out->bn = fp64_bn(t);
   out->bk = kBK;

@@ -184,7 +184,7 @@ struct mmp_server {
         continue;
       }
       if (r.plan.form == MMP_FORM_FP64_WORDS) {
-        f64[std::make_tuple(r.plan.u, r.plan.v, r.plan.tile, fp64_fe(r.plan.slots))].push_back(
+        f64[std::make_tuple(r.plan.u, r.plan.v, r.plan.tile, fp64_class(r.plan.slots, r.plan.kblock))].push_back(
             make_fp64_args(r.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc));
       } else {
         Int8Args g = make_int8_args(r.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc,

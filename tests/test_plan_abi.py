@@ -380,17 +380,19 @@ def test_tune_cache_entry_that_does_not_fit_is_ignored(tmp_path):
 
 # ------------------------------------------------------------------ centered words
 # The opt-in centered words: x -> x - p when 2x > p, then a split with
-# quotients rounded to nearest (rint of a correctly rounded division), and
+# quotients rounded to nearest (floor of fl(t fl(1/a) + 1/2)), and
 # the in-loop reduction c = floor(fl(x q + 1/2)), d = x - c p.  Emulated
 # exactly in binary64 (Python floats are IEEE binary64 with round-to-nearest-
 # even; pa.fma rounds once).
 
 
 def _centered_words(x, p, a, u):
+    # the kernel's split: r = floor(fl(t fl(1/a) + 1/2)), one rounding (fma)
     t = x - p if 2 * x > p else x
+    ainv = 1.0 / a
     w = []
     for _ in range(u - 1):
-        r = round(float(t) / float(a))  # rint: ties to even, as the kernel's rint
+        r = math.floor(pa.fma(float(t), ainv, 0.5))
         w.append(t - r * a)
         t = r
     w.append(t)
