@@ -79,7 +79,9 @@ typedef struct {
                              where its range check allows (see mmp_plan_t) */
   int64_t force_kblock;   /* 0: planner's k-block; else the number of k-terms
                              accumulated between reductions (<= the bound;
-                             INT8 form: a multiple of 64 up to kblock_int8) */
+                             FP64 form: at most 16, or a multiple of 4 up to
+                             2^26; INT8 form: a multiple of 64 up to
+                             kblock_int8) */
   void *workspace;        /* optional caller-owned device workspace; when
                              NULL the library allocates stream-ordered memory
                              from the device's default pool.  Pass one (of at
@@ -123,7 +125,8 @@ typedef struct {
                              eq. cAcB otherwise (FP64 form) */
   int64_t kblock;         /* k-terms accumulated between reductions (<= lambda) */
   int slots;              /* MFMA k-slots that hold one k-block (>= kblock;
-                             the excess slots hold zeros) */
+                             4, 8 or 16 with the excess slots holding zeros,
+                             or equal to kblock, a multiple of 4) */
   int lazy;               /* 1: in-loop reductions omit Alg. 1's corrections
                              (result in [-p, 2p), or [-2^t, -2^t + 4p) with
                              extended); the final one is complete */

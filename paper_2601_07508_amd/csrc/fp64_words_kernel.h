@@ -343,7 +343,8 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
   // global loads are issued one further iteration ahead, so they are in
   // flight during a whole stage of MFMAs.  One barrier per stage: after it,
   // every wave has finished reading the buffer the next store overwrites.
-  int stage_in_block = 0;
+  int kc = 0;                           // k-steps since the last in-loop reduction
+  const int kpb = a.ksteps_per_block;  // FE == 4: k-steps per block (S / 4)
   __syncthreads();  // the zeroed buffers are visible before any store
   if (s_begin < s_end) {
     load_stage(s_begin * KR);
@@ -376,12 +377,11 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
                   __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][x], bf[j][y], acc[i][j][x][y], 0, 0, 0);
       if constexpr (FE < 4) {
         if ((ks + 1) % FE == 0) reduce_all();
-      }
-    }
-    if constexpr (FE == 4) {
-      if (++stage_in_block == a.stages_per_block) {
-        stage_in_block = 0;
-        reduce_all();
+      } else {  // blocks of any whole number of k-steps, across stages
+        if (++kc == kpb) {
+          kc = 0;
+          reduce_all();
+        }
       }
     }
     if (s + 1 < s_end) {

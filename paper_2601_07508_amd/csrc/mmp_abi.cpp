@@ -165,8 +165,9 @@ Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, c
   a.bfix = (pl.v > 1 && !is_pow2(pl.beta)) ? 1 : 0;
   a.L = (int)pl.kblock;
   a.S = pl.slots;
-  a.KR = (pl.slots <= kBK) ? (kBK / pl.slots) * (int)pl.kblock : kBK;
-  a.stages_per_block = pl.slots >= kBK ? pl.slots / kBK : 1;
+  // real k-terms per 16-slot stage: fewer only when blocks leave zero slots
+  a.KR = (pl.slots <= kBK && pl.kblock < pl.slots) ? (kBK / pl.slots) * (int)pl.kblock : kBK;
+  a.ksteps_per_block = pl.slots / 4;
   a.lazy = pl.lazy;
   a.splits = 1;
   if (pl.extended) {

@@ -91,7 +91,7 @@ struct Fp64Args {
   int L;           // real k-terms per block
   int S;           // k-slots per block (S >= L; zeros fill the rest)
   int KR;          // real k-terms per LDS stage
-  int stages_per_block;  // S >= 16: LDS stages per block (S / 16)
+  int ksteps_per_block;  // S / 4: MFMA k-steps per block (S >= 12 or a padded 16-slot stage)
   int lazy;              // in-loop reductions without corrections
   double bias;           // K in the in-loop reduction c = floor(x q + K) (0, or floor(2^t / p) - 1)
   double acc_init;       // accumulator start value: -K p (congruent to 0)
@@ -175,7 +175,7 @@ struct Fp64Batch {
 // (1, 2 or 4), PAD = blocks leave zero slots in a stage (L < S <= 16).
 // Jobs of one launch share it.
 inline int fp64_class(int slots, int64_t kblock) {
-  const int fe = slots == 4 ? 1 : slots == 8 ? 2 : 4;
+  const int fe = slots == 4 ? 1 : slots == 8 ? 2 : 4;  // 4: a k-step counter, any S = 4j >= 12
   const int pad = (slots <= kBK && kblock < slots) ? 1 : 0;
   return 2 * fe + pad;
 }

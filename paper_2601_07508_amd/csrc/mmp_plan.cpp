@@ -165,13 +165,11 @@ KBlock choose_kblock(uint64_t p, int u, int v, int64_t k, bool strict, bool allo
     const bool ext = e == 1;
     const int64_t lambda = ext ? lam_ext : lam_paper;
     for (int S : {4, 8, 16}) consider(S, lambda < S ? lambda : S, ext);
-    // multi-stage blocks (no zero slots): L = S = 16 j
-    const int64_t jmax = lambda / kBK;
-    if (jmax >= 2) {
-      const int64_t cap = (int64_t)1 << 26;  // beyond this the in-loop cost is nil
-      const int64_t j = jmax * kBK > cap ? cap / kBK : jmax;
-      consider((int)std::min<int64_t>(j * kBK, cap), j * kBK, ext);
-    }
+    // longer blocks of whole k-steps, no zero slots: L = S = 4 j >= 12
+    // (the kernel counts k-steps, so a block may end inside a stage)
+    const int64_t cap = (int64_t)1 << 26;  // beyond this the in-loop cost is nil
+    const int64_t L4 = std::min<int64_t>(lambda, cap) / 4 * 4;
+    if (L4 >= 12 && L4 != kBK) consider((int)L4, L4, ext);
   }
   return best;
 }
@@ -416,8 +414,8 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     if (L <= 4) S = 4;
     else if (L <= 8) S = 8;
     else if (L <= kBK) S = kBK;
-    else if (L % kBK == 0) S = (int)std::min<int64_t>(L, (int64_t)1 << 26);
-    else return MMP_EINVAL;  // longer blocks must be whole LDS stages
+    else if (L % 4 == 0) S = (int)L;
+    else return MMP_EINVAL;  // longer blocks must be whole MFMA k-steps
     if (L > ((int64_t)1 << 26)) return MMP_EINVAL;
     bk = {L, S, centered || ext || (!strict && lazy_block_ok(p, bu, bv, L)), ext, block_cost(S, L, false)};
   } else if (u != 0) {
@@ -444,7 +442,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->q = 1.0 / (double)p;
   out->est_seconds = fp64_seconds(m, n, k, bu * bv, bk.cost);
   {
-    const int64_t KR = bk.S <= kBK ? (kBK / bk.S) * bk.L : kBK;
+    const int64_t KR = (bk.S <= kBK && bk.L < bk.S) ? (kBK / bk.S) * bk.L : kBK;
     const int64_t tiles = cdiv(m, out->bm) * cdiv(n, out->bn);
     out->splits = o.splits ? o.splits : choose_splits(tiles, cdiv(k, KR), 64);
     out->workspace_bytes = out->splits > 1 ? 8 * (size_t)out->splits * (size_t)m * (size_t)n : 0;

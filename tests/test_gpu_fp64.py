@@ -103,7 +103,7 @@ def test_worst_case_at_bitsize_limit(uv, bits):
                                    (4503599627370449, 2, 3)])
 def test_every_forced_kblock(p, u, v):
     lam = pa.block_size(p, u, v)
-    Ls = list(range(1, min(lam, 16) + 1)) + ([32, 48] if lam >= 48 else [])
+    Ls = list(range(1, min(lam, 16) + 1)) + [L for L in (20, 28, 32, 48) if L <= lam]
     m, n, k = 33, 47, 203
     A = gen.random_matrix(11, 1, m, k, p)
     B = np.full((k, n), p - 1, dtype=np.uint64)
@@ -309,7 +309,7 @@ def test_centered_forced_kblock_up_to_bound(p, u, v):
     B = np.full((k, n), y, dtype=np.uint64)
     want = oracle.mm_modp(p, A, B)
     ok = 0
-    for L in list(range(1, 17)) + [32, 48, 64, 112]:
+    for L in list(range(1, 17)) + [20, 28, 32, 48, 64, 112]:
         try:
             mmp.plan(p, m, n, k, u, v, centered_words=True, force_kblock=L)
         except mmp.MmpError:

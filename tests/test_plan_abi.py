@@ -91,7 +91,7 @@ def test_plan_invariants(p, uv, k):
         pl = mmp.plan(p, 256, 256, k, u, v, strict_fmod=strict)
         L, S = pl["kblock"], pl["slots"]
         assert 1 <= L <= lam
-        assert S >= L and (S in (4, 8, 16) or (S % 16 == 0 and S == L))
+        assert S >= L and (S in (4, 8, 16) or (S % 4 == 0 and S == L and S >= 12))
         if pl["lazy"]:
             assert not strict and _tight_lazy_ok(p, u, v, L)
         assert pl["q"] == 1.0 / p
@@ -155,8 +155,9 @@ def test_forced_kblock():
     assert e.value.status == -2
     p = 68719476731  # (2,2): lambda = 131071
     assert mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=4096)["slots"] == 4096
+    assert mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=100)["slots"] == 100  # 25 whole k-steps
     with pytest.raises(mmp.MmpError):
-        mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=100)  # > 16 and not whole stages
+        mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=102)  # > 16 and not whole k-steps
 
 
 def test_reserved_options_rejected():
@@ -335,7 +336,7 @@ def test_extended_doubles_block_at_50_bits():
     p = 1125899906842597
     assert mmp.plan(p, 64, 64, 4096, 2, 2)["kblock"] == 4       # paper: lambda = 7, MFMA-aligned 4
     pl = mmp.plan(p, 64, 64, 4096, 2, 2, extended_block=True)
-    assert pl["kblock"] == 8 and pl["lambda"] == 7              # extended: 11 allowed, 8 aligned
+    assert pl["kblock"] == 12 and pl["lambda"] == 7             # extended: 12 allowed, 3 k-steps
     with pytest.raises(mmp.MmpError):
         mmp.plan(p, 64, 64, 64, 2, 2, extended_block=True, strict_fmod=True)
 
@@ -515,7 +516,7 @@ def test_centered_longest_block_is_the_bound():
 def test_centered_quadruples_block_at_50_bits():
     p = 1125899906842597
     pl = mmp.plan(p, 8192, 8192, 8192, 2, 2, centered_words=True)
-    assert (pl["kblock"], pl["slots"], pl["centered"]) == (16, 16, 1)  # 29 allowed, one LDS stage
+    assert (pl["kblock"], pl["slots"], pl["centered"]) == (28, 28, 1)  # 29 allowed, 7 k-steps
     assert mmp.plan(p, 8192, 8192, 8192, 2, 2)["kblock"] == 4
     # centered words reach one bit past the paper's (1,1) limit of 26 bits
     p27 = gen.prev_prime(1 << 27)
