@@ -194,15 +194,18 @@ struct I8Shape {
 
 // Ring of two LDS stages; each holds D digit planes of a BM x 64 slab of A
 // and of a BN x 64 slab of B^T, 64 bytes per row with no padding.  The four
-// 16-byte chunks of row r are stored in the order q ^ ((r >> 2) & 3), so the
-// 16 rows that one MFMA operand read touches fall in 16 distinct bank groups.
+// 16-byte chunks of row r are stored in the order q ^ f(r) with
+// f(r) = ((r >> 2) ^ (r >> 1)) & 3.  An operand read takes chunk q of 16
+// consecutive rows; f keeps those chunks in distinct banks whether the LDS
+// serves 16 lanes over 256 bytes (distinct (r & 3, q ^ f)) or 8 lanes over
+// 128 bytes (distinct (r & 1, q ^ f) within each 8 rows).
 constexpr int kStages = 2;
 template <int D, int BM, int BN>
 struct DigitRing {
   int8_t s[kStages][D][BM + BN][64];
 };
 
-__device__ __forceinline__ int swz(int r, int q) { return ((q ^ (r >> 2)) & 3) * 16; }
+__device__ __forceinline__ int swz(int r, int q) { return ((q ^ (r >> 2) ^ (r >> 1)) & 3) * 16; }
 
 // wait until at most N vector-memory operations of this wave are outstanding
 template <int N>
@@ -235,37 +238,48 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
   const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int64_t planeA = m * kp, planeB = n * kp;
   const int rl = lane >> 2;                       // row within a 16-row group
-  const int ql = (lane & 3) ^ ((lane >> 4) & 3);  // chunk this lane copies
+  const int ql = (lane & 3) ^ (((lane >> 4) ^ (lane >> 3)) & 3);  // chunk this lane copies: f(rl)
 
-  const int8_t* src[IPW];
-  int dst_plane[IPW], dst_row[IPW];
+  // Copies move 16 rows x 64 bytes of one digit plane straight into LDS
+  // (global_load_lds, 16 bytes a lane).  Each lane's byte offset within its
+  // plane (row rl of the copy's 16, chunk ql; rows past m or n read the last
+  // row instead, feeding outputs that are never stored) is fixed for the
+  // whole loop; only the plane's scalar base moves by 64 bytes a stage.  The
+  // wave index is made uniform once, so a copy's plane, base and LDS
+  // destination are scalars and a stage's copies need no vector work.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  uint32_t voff[IPW];
 #pragma unroll
   for (int e = 0; e < IPW; e++) {
-    const int t = wave + NW * e;
+    const int t = wv + NW * e;
     if (t < D * BM / 16) {
-      const int i = t / (BM / 16), g = t % (BM / 16);
-      int64_t row = m0 + 16 * g + rl;
-      row = row < m ? row : m - 1;
-      src[e] = Ad + i * planeA + row * kp + 16 * ql;
-      dst_plane[e] = i;
-      dst_row[e] = 16 * g;
+      const int64_t row = m0 + 16 * (t % (BM / 16)) + rl;
+      voff[e] = (uint32_t)((row < m ? row : m - 1) * kp + 16 * ql);
     } else {
-      const int t2 = t - D * BM / 16;
-      const int i = t2 / (BN / 16), g = t2 % (BN / 16);
-      int64_t col = n0 + 16 * g + rl;
-      col = col < n ? col : n - 1;
-      src[e] = Bd + i * planeB + col * kp + 16 * ql;
-      dst_plane[e] = i;
-      dst_row[e] = BM + 16 * g;
+      const int64_t row = n0 + 16 * ((t - D * BM / 16) % (BN / 16)) + rl;
+      voff[e] = (uint32_t)((row < n ? row : n - 1) * kp + 16 * ql);
     }
   }
   auto issue = [&](int64_t st) {
     const int b = (int)(st & 1);
 #pragma unroll
-    for (int e = 0; e < IPW; e++)
-      __builtin_amdgcn_global_load_lds((const void*)(src[e] + st * 64),
-                                       (__attribute__((address_space(3))) void*)&sm.s[b][dst_plane[e]][dst_row[e]][0],
-                                       16, 0, 0);
+    for (int e = 0; e < IPW; e++) {
+      const int t = wv + NW * e;
+      const int8_t* base;
+      int plane, row0;
+      if (t < D * BM / 16) {
+        plane = t / (BM / 16);
+        row0 = 16 * (t % (BM / 16));
+        base = Ad + plane * planeA + st * 64;
+      } else {
+        const int t2 = t - D * BM / 16;
+        plane = t2 / (BN / 16);
+        row0 = BM + 16 * (t2 % (BN / 16));
+        base = Bd + plane * planeB + st * 64;
+      }
+      __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
+                                       (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
+    }
   };
 
   const int lrow = lane & 15, lq = lane >> 4;
