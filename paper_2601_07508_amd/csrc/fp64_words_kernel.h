@@ -157,10 +157,12 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
   int job = 0;
   while (job + 1 < bt.njobs && (int)blockIdx.x >= bt.tile_start[job + 1]) job++;
   const Fp64Args& a = bt.job[job];
-  // split-K: tiles of one k-range are consecutive; split index major
-  const int tiles = (int)(((a.m + 2 * TM * 16 - 1) / (2 * TM * 16)) * ((a.n + 2 * TN * 16 - 1) / (2 * TN * 16)));
-  const int split = ((int)blockIdx.x - bt.tile_start[job]) / tiles;
-  const int local_bid = ((int)blockIdx.x - bt.tile_start[job]) - split * tiles;
+  // split-K: the k-range varies fastest over workgroup ids, so with 8 (or
+  // 16, ...) k-ranges each XCD of the round-robin dispatch reads only its
+  // own k-range of A and B
+  const int bid = (int)blockIdx.x - bt.tile_start[job];
+  const int split = a.splits > 1 ? bid % a.splits : 0;
+  const int local_bid = a.splits > 1 ? bid / a.splits : bid;
   constexpr int BM = 2 * TM * 16;
   constexpr int BN = 2 * TN * 16;
   constexpr int LDA = kBK + kPadA;

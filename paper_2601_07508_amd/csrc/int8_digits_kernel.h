@@ -12,7 +12,8 @@
 // exact when K * min(D_A, D_B) * 2^14 <= 2^31 - 1 (|d_i d_j| <= 2^14).
 // After each block the accumulators are folded into a binary64 residue:
 //     t = sum_s 256^s D_s mod p  (Horner's rule from the top weight down;
-//         256 t is exact in binary64 and each step is reduced with Alg. 1),
+//         256 t is exact in binary64 and each step is reduced with Alg. 1's
+//         quotient rounded to nearest, see fold_weights),
 //     F = F + t mod p,
 // and C = F is written once.  All binary64 steps follow Section 2.1.
 #pragma once
@@ -36,6 +37,25 @@ __device__ __forceinline__ double fmod_full(double x, double p, double q) {
   d = (d >= p) ? d - p : d;
   d = (d < 0.0) ? d + p : d;
   return d;
+}
+
+// Horner's rule over the 2D - 1 digit weights: a value in [0, p) congruent
+// to sum_s 256^s w[s], |w[s]| < 2^31.  Each step scales by 256 (exact: a
+// power of two), reduces with Alg. 1's quotient rounded to nearest instead
+// of floored (c = floor(fl(x q + 1/2)), no corrections), and adds the next
+// weight.  With |x| < 2^61 the quotient estimate is within |x| 2^-52 / p of
+// x / p + 1/2, so the reduced value stays within p/2 + 2^10 of zero and the
+// sum with a weight stays below 2^53, exact.  One complete reduction ends it.
+template <int ND>
+__device__ __forceinline__ double fold_weights(const int (&w)[ND], double p, double q) {
+  double t = (double)w[ND - 1];
+#pragma unroll
+  for (int s = ND - 2; s >= 0; s--) {
+    const double x = 256.0 * t;
+    const double c = floor(fma(x, q, 0.5));
+    t = fma(-c, p, x) + (double)w[s];
+  }
+  return fmod_full(t, p, q);
 }
 
 __device__ __forceinline__ double addmod(double x, double y, double p) {
@@ -343,9 +363,13 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
-  // split-K: tiles of one k-range are consecutive; split index major
-  const int split = ((int)blockIdx.x - bt.tile_start[job]) / (nbm * nbn);
-  const int local_bid = ((int)blockIdx.x - bt.tile_start[job]) - split * nbm * nbn;
+  // split-K: the k-range varies fastest over workgroup ids.  Dispatch is
+  // round-robin over the 8 XCDs, so with 8 (or 16, ...) k-ranges each XCD
+  // works on its own k-range for every tile and reads that part of the
+  // planes once into its L2, instead of every XCD reading all of A.
+  const int bid = (int)blockIdx.x - bt.tile_start[job];
+  const int split = a.splits > 1 ? bid % a.splits : 0;
+  const int local_bid = a.splits > 1 ? bid / a.splits : bid;
   const int64_t nst = a.kp / kBK8, per_split = (nst + a.splits - 1) / a.splits;
   const int64_t st_begin = (int64_t)split * per_split;
   const int64_t st_end = st_begin + per_split < nst ? st_begin + per_split : nst;
@@ -377,13 +401,10 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
       for (int y = 0; y < TN; y++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          double t = fmod_full((double)acc[ND - 1][x][y][r], p, q);
+          int w[ND];
 #pragma unroll
-          for (int s = ND - 2; s >= 0; s--) {
-            t = fmod_full(256.0 * t, p, q);                    // 256 t is exact
-            t = fmod_full(t + (double)acc[s][x][y][r], p, q);  // |acc| < 2^31: exact sum
-          }
-          F[x][y][r] = addmod(F[x][y][r], t, p);
+          for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
+          F[x][y][r] = addmod(F[x][y][r], fold_weights<ND>(w, p, q), p);
         }
 #pragma unroll
     for (int s = 0; s < ND; s++)
@@ -464,12 +485,10 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
         const int64_t col = n0 + wn + y * 16 + lrow;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          double t = fmod_full((double)acc[ND - 1][x][y][r], p, q);
+          int w[ND];
 #pragma unroll
-          for (int s = ND - 2; s >= 0; s--) {
-            t = fmod_full(256.0 * t, p, q);
-            t = fmod_full(t + (double)acc[s][x][y][r], p, q);
-          }
+          for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
+          const double t = fold_weights<ND>(w, p, q);
           const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
           if (row < a.m && col < a.n) C[row * a.ldc + col] = t + 0.0;
         }

@@ -196,11 +196,13 @@ double int8_seconds(int64_t m, int64_t n, int64_t k, int d) {
   return gemm + digitize + fold + 3 * 4e-6;
 }
 
-int pick_tile(int u, int v, int64_t m, int64_t n) {
+// The largest tile that fills the chip (two workgroups per CU), counting
+// the k-ranges split-K adds for long k; else the smallest.
+int pick_tile(int u, int v, int64_t m, int64_t n, int64_t stages) {
   for (int id = 1; id <= 3; id++) {
     Fp64Tile t = fp64_tile(id, u, v);
     int64_t nb = cdiv(m, fp64_bm(t)) * cdiv(n, fp64_bn(t));
-    if (nb >= 512) return id;
+    if (nb * choose_splits(nb, stages, 64) >= 512) return id;
   }
   return 3;
 }
@@ -434,7 +436,8 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->lazy = bk.lazy ? 1 : 0;
   out->extended = bk.extended ? 1 : 0;
   out->centered = centered ? 1 : 0;
-  out->tile = o.tile ? o.tile : pick_tile(bu, bv, m, n);
+  const int64_t KR = (bk.S <= kBK && bk.L < bk.S) ? (kBK / bk.S) * bk.L : kBK;  // real k-terms per stage
+  out->tile = o.tile ? o.tile : pick_tile(bu, bv, m, n, cdiv(k, KR));
   Fp64Tile t = fp64_tile(out->tile, bu, bv);
   out->bm = fp64_bm(t);
   out->bn = fp64_bn(t);
@@ -442,7 +445,6 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->q = 1.0 / (double)p;
   out->est_seconds = fp64_seconds(m, n, k, bu * bv, bk.cost);
   {
-    const int64_t KR = (bk.S <= kBK && bk.L < bk.S) ? (kBK / bk.S) * bk.L : kBK;
     const int64_t tiles = cdiv(m, out->bm) * cdiv(n, out->bn);
     out->splits = o.splits ? o.splits : choose_splits(tiles, cdiv(k, KR), 64);
     out->workspace_bytes = out->splits > 1 ? 8 * (size_t)out->splits * (size_t)m * (size_t)n : 0;

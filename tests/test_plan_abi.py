@@ -529,3 +529,43 @@ def test_centered_option_conflicts(bad):
     with pytest.raises(mmp.MmpError):
         mmp.plan(1125899906842597, 64, 64, 64, 0 if bad.get("form") else 2, 0 if bad.get("form") else 2,
                  centered_words=True, **bad)
+
+
+# ------------------------------------------------------------------ INT8 digit-weight fold
+# The INT8 form folds its 2D - 1 int32 digit-weight accumulators with
+# Horner's rule: t <- (256 t - c p) + w[s], c = floor(fl(256 t q + 1/2)).
+# Emulated here step by step in binary64 (pa.fma rounds once): every
+# intermediate must be an exactly representable integer and the result must
+# be sum 256^s w[s] mod p.
+
+
+def _fold_weights(w, p):
+    q = 1.0 / p
+    t = float(w[-1])
+    for s in range(len(w) - 2, -1, -1):
+        x = 256.0 * t
+        assert x == 256 * int(t) and abs(x) < 2.0 ** 61
+        c = math.floor(pa.fma(x, q, 0.5))
+        d = int(x) - c * p  # the fma's exact result when representable
+        assert abs(d) <= p // 2 + 2 ** 10 and float(d) == d
+        t = float(d + w[s])
+        assert t == d + w[s] and abs(t) < 2.0 ** 53
+    c = math.floor(t * q)
+    d = int(t) - c * p
+    d = d - p if d >= p else d
+    d = d + p if d < 0 else d
+    return d
+
+
+@pytest.mark.parametrize("p", [5, 7, 1048573, 2147483647, 68719476731, 1125899906842597,
+                               4503599627370449])
+def test_int8_fold_exact(p):
+    lim = 2 ** 31 - 1
+    rng = gen.uniform_mod(p % 1000, 91, 4000, 2 * lim + 1)
+    vals = [int(x) - lim for x in rng]
+    for nd in (1, 3, 5, 9, 13, 15):
+        cases = [[lim] * nd, [-lim] * nd, [lim, -lim] * (nd // 2) + [lim] * (nd % 2)]
+        cases += [vals[i * nd:(i + 1) * nd] for i in range(len(vals) // nd)][:60]
+        for w in cases:
+            want = sum(256 ** s * ws for s, ws in enumerate(w)) % p
+            assert _fold_weights(w, p) == want
