@@ -424,10 +424,10 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
 }
 
 // The tile shapes of fp64_tile_c() as compile-time constants.
-template <int U, int V, int ID>
+template <int U, int V, int ID, bool WIDE>
 struct TileOf {
-  static constexpr int tm = fp64_tile_c(ID, U, V).tm;
-  static constexpr int tn = fp64_tile_c(ID, U, V).tn;
+  static constexpr int tm = fp64_tile_c(ID, U, V, WIDE).tm;
+  static constexpr int tn = fp64_tile_c(ID, U, V, WIDE).tn;
 };
 
 // Tiles of one product for a given shape.
@@ -438,7 +438,8 @@ inline int64_t tiles_of(const Fp64Args& a) {
 
 template <int U, int V, int ID, int FE, bool PAD>
 int launch_shape(const Fp64Batch& b0, hipStream_t s) {
-  constexpr int TM = TileOf<U, V, ID>::tm, TN = TileOf<U, V, ID>::tn;
+  constexpr bool WIDE = FE == 4 && !PAD;  // fp64_wide() of the launch's class
+  constexpr int TM = TileOf<U, V, ID, WIDE>::tm, TN = TileOf<U, V, ID, WIDE>::tn;
   constexpr int BM = 2 * 16 * TM, BN = 2 * 16 * TN;
   Fp64Batch b = b0;
   int64_t total = 0;

@@ -31,17 +31,23 @@ struct Fp64Tile {
 // Tile 1, the large shape, keeps each word pair within 256 VGPRs and two
 // workgroups per CU (LDS): the longer side goes to the operand with fewer
 // words, whose fragments are the cheaper ones to hold.
-constexpr Fp64Tile fp64_tile_c(int tile_id, int u, int v) {
+// wide: the kernel class reduces only every whole number of k-steps >= 3
+// and has no padded stages (fewer live registers), which lets (1,1) take
+// 4 x 4 tiles.
+constexpr Fp64Tile fp64_tile_c(int tile_id, int u, int v, bool wide) {
   if (tile_id == 3) return Fp64Tile{1, 1};
   if (tile_id == 2) return u * v <= 2 ? Fp64Tile{2, 2} : u * v <= 4 ? Fp64Tile{1, 2} : Fp64Tile{1, 1};
-  if (u == 1 && v == 1) return Fp64Tile{4, 2};
+  if (u == 1 && v == 1) return wide ? Fp64Tile{4, 4} : Fp64Tile{4, 2};
   if (u * v == 2) return u < v ? Fp64Tile{4, 2} : Fp64Tile{2, 4};
   if (u == 1 && v == 4) return Fp64Tile{4, 1};
   if (u == 4 && v == 1) return Fp64Tile{1, 4};
   if (u * v <= 4) return Fp64Tile{2, 2};  // (1,3), (3,1), (2,2)
   return u >= v ? Fp64Tile{1, 2} : Fp64Tile{2, 1};
 }
-inline Fp64Tile fp64_tile(int tile_id, int u, int v) { return fp64_tile_c(tile_id, u, v); }
+inline bool fp64_wide(int slots, int64_t kblock) { return slots > 8 && !(slots <= 16 && kblock < slots); }
+inline Fp64Tile fp64_tile(int tile_id, int u, int v, int slots, int64_t kblock) {
+  return fp64_tile_c(tile_id, u, v, fp64_wide(slots, kblock));
+}
 inline int fp64_bm(const Fp64Tile& t) { return 2 * 16 * t.tm; }
 inline int fp64_bn(const Fp64Tile& t) { return 2 * 16 * t.tn; }
 

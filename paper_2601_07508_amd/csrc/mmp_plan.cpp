@@ -198,9 +198,9 @@ double int8_seconds(int64_t m, int64_t n, int64_t k, int d) {
 
 // The largest tile that fills the chip (two workgroups per CU), counting
 // the k-ranges split-K adds for long k; else the smallest.
-int pick_tile(int u, int v, int64_t m, int64_t n, int64_t stages) {
+int pick_tile(int u, int v, int64_t m, int64_t n, int64_t stages, int slots, int64_t kblock) {
   for (int id = 1; id <= 3; id++) {
-    Fp64Tile t = fp64_tile(id, u, v);
+    Fp64Tile t = fp64_tile(id, u, v, slots, kblock);
     int64_t nb = cdiv(m, fp64_bm(t)) * cdiv(n, fp64_bn(t));
     if (nb * choose_splits(nb, stages, 64) >= 512) return id;
   }
@@ -437,8 +437,8 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->extended = bk.extended ? 1 : 0;
   out->centered = centered ? 1 : 0;
   const int64_t KR = (bk.S <= kBK && bk.L < bk.S) ? (kBK / bk.S) * bk.L : kBK;  // real k-terms per stage
-  out->tile = o.tile ? o.tile : pick_tile(bu, bv, m, n, cdiv(k, KR));
-  Fp64Tile t = fp64_tile(out->tile, bu, bv);
+  out->tile = o.tile ? o.tile : pick_tile(bu, bv, m, n, cdiv(k, KR), bk.S, bk.L);
+  Fp64Tile t = fp64_tile(out->tile, bu, bv, bk.S, bk.L);
   out->bm = fp64_bm(t);
   out->bn = fp64_bn(t);
   out->bk = kBK;
