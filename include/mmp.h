@@ -165,7 +165,13 @@ typedef struct {
 int mm_modp(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k,
             const double *A, const double *B, double *C);
 
-/* Same product with options, strides and a stream; asynchronous. */
+/* Same product with options, strides and a stream; asynchronous.
+   The FP64-word kernel addresses one stage of A (a tile's rows) and of B
+   (16 rows) with 32-bit byte offsets: (bm - 1) lda + 16 and 16 ldb + bn
+   doubles must stay below 2^28.  Beyond that an AUTO call (u = v = 0, no
+   word-form option) takes the INT8-digit form, and a call that forces the
+   FP64 form returns MMP_EINVAL before any device work.  Batched products
+   return MMP_EINVAL; the server plans such a request in the INT8 form. */
 int mm_modp_async(const mmp_opts *opts, uint64_t p, int u, int v, int64_t m,
                   int64_t n, int64_t k, const double *A, int64_t lda,
                   const double *B, int64_t ldb, double *C, int64_t ldc,

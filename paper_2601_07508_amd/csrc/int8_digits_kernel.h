@@ -268,16 +268,16 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
   // wave index is made uniform once, so a copy's plane, base and LDS
   // destination are scalars and a stage's copies need no vector work.
   const int wv = __builtin_amdgcn_readfirstlane(wave);
-  uint32_t voff[IPW];
+  uint64_t voff[IPW];
 #pragma unroll
   for (int e = 0; e < IPW; e++) {
     const int t = wv + NW * e;
     if (t < D * BM / 16) {
       const int64_t row = m0 + 16 * (t % (BM / 16)) + rl;
-      voff[e] = (uint32_t)((row < m ? row : m - 1) * kp + 16 * ql);
+      voff[e] = (uint64_t)((row < m ? row : m - 1) * kp + 16 * ql);
     } else {
       const int64_t row = n0 + 16 * ((t - D * BM / 16) % (BN / 16)) + rl;
-      voff[e] = (uint32_t)((row < n ? row : n - 1) * kp + 16 * ql);
+      voff[e] = (uint64_t)((row < n ? row : n - 1) * kp + 16 * ql);
     }
   }
   auto issue = [&](int64_t st) {

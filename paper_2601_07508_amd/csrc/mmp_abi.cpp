@@ -58,6 +58,12 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
+bool fp64_ld_ok(const mmp_plan_t& pl, int64_t lda, int64_t ldb) {
+  if (pl.form != MMP_FORM_FP64_WORDS) return true;
+  const int64_t lim = (int64_t)1 << 31;
+  return ((int64_t)(pl.bm - 1) * lda + kBK) * 8 < lim && ((int64_t)kBK * ldb + pl.bn) * 8 < lim;
+}
+
 int check_product_args(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
                        int64_t ldb, const double* C, int64_t ldc) {
   if (m < 0 || n < 0 || k < 0) return MMP_EINVAL;
@@ -261,6 +267,18 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
     if (int st = check_product_args(m, n, k, A, lda, B, ldb, C, ldc)) return st;
     mmp_plan_t pl;
     if (int st = mmp::plan(p, u, v, m, n, k, opts, &pl)) return st;
+    if (!fp64_ld_ok(pl, lda, ldb)) {
+      // leading dimensions beyond the FP64 kernel's offsets: an AUTO plan
+      // takes the INT8 form, which has no such limit; a forced one fails
+      if (u != 0 || (opts && (opts->form != MMP_FORM_AUTO || opts->tile || opts->force_kblock ||
+                              opts->extended_block || opts->centered_words)))
+        return MMP_EINVAL;
+      mmp_opts o2;
+      std::memset(&o2, 0, sizeof(o2));
+      if (opts) o2 = *opts;
+      o2.form = MMP_FORM_INT8_WORDS;
+      if (int st = mmp::plan(p, 0, 0, m, n, k, &o2, &pl)) return st;
+    }
     if (m == 0 || n == 0) return MMP_OK;
     if (k == 0) return hip_status(launch_zero_fill(C, m, n, ldc, stream));
     if (opts && opts->validate_entries)

@@ -54,6 +54,7 @@ int plan_batch(const mmp_job* jobs, int count, const mmp_opts* opts, std::vector
     Planned pj;
     pj.job = &j;
     if (int st = mmp::plan(j.p, j.u, j.v, j.m, j.n, j.k, opts, &pj.plan)) return st;
+    if (!fp64_ld_ok(pj.plan, j.lda, j.ldb)) return MMP_EINVAL;
     pj.ws_offset = ws;
     if (pj.plan.form == MMP_FORM_INT8_WORDS && j.m > 0 && j.n > 0 && j.k > 0)
       ws += align_up(pj.plan.workspace_bytes);

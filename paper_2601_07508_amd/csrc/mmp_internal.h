@@ -201,6 +201,9 @@ int launch_reduce_mod(const uint64_t* X, int64_t rows, int64_t cols, int64_t ld,
 int hip_status(int err);
 bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes);
 size_t span_bytes(int64_t rows, int64_t cols, int64_t ld);
+// The FP64-word kernel addresses a stage's slabs with 32-bit byte offsets:
+// BM rows of A and 16 k-rows of B must span less than 2^31 bytes.
+bool fp64_ld_ok(const mmp_plan_t& pl, int64_t lda, int64_t ldb);
 int check_product_args(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
                        int64_t ldb, const double* C, int64_t ldc);
 int acquire_workspace(size_t bytes, const mmp_opts* opts, void* stream, void** out, bool* owned);

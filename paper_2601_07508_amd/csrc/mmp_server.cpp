@@ -403,6 +403,11 @@ int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
     std::memset(&o1, 0, sizeof(o1));
     o1.splits = 1;  // requests run whole; concurrency comes from the mix
     if (int st = mmp::plan(j.p, j.u, j.v, j.m, j.n, j.k, &o1, &r.plan)) return st;
+    if (!fp64_ld_ok(r.plan, j.lda, j.ldb)) {  // an AUTO request takes the INT8 form instead
+      if (j.u != 0) return MMP_EINVAL;
+      o1.form = MMP_FORM_INT8_WORDS;
+      if (int st = mmp::plan(j.p, 0, 0, j.m, j.n, j.k, &o1, &r.plan)) return st;
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (r.plan.form == MMP_FORM_INT8_WORDS) {
       const int64_t kp = (j.k + 63) / 64 * 64;

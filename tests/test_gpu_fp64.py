@@ -338,3 +338,35 @@ def test_centered_equals_paper_words_large():
     R, Cc = np.meshgrid(rr, cc, indexing="ij")
     want = oracle.mm_modp_entries(p, A, B, R.ravel(), Cc.ravel()).astype(np.float64)
     assert np.array_equal(C1.cpu().numpy()[R.ravel(), Cc.ravel()], want)
+
+
+@pytest.mark.parametrize("splits", [2, 8])
+def test_centered_and_extended_with_split_k(splits):
+    # k-ranges of the opt-in bounds: each range's residues are exact
+    for p, (u, v), kw in [(1125899906842597, (2, 2), dict(centered_words=True)),
+                          (1125899906842597, (2, 2), dict(extended_block=True)),
+                          (33554393, (1, 1), dict(centered_words=True))]:
+        m, n, k = 70, 90, 4096 + 37
+        A = gen.random_matrix(splits + 5, 1, m, k, p)
+        B = gen.random_matrix(splits + 5, 2, k, n, p)
+        say("splitk", p, u, v, kw, splits)
+        assert mmp.plan(p, m, n, k, u, v, splits=splits, **kw)["splits"] == splits
+        assert_exact(run(p, A, B, u, v, splits=splits, **kw), oracle.mm_modp(p, A, B))
+
+
+def test_centered_in_a_batch():
+    # one launch per kernel class; the centered option applies to every job
+    jobs, host = [], []
+    for i, (p, u, v) in enumerate([(1125899906842597, 2, 2), (1125899906842597, 2, 2), (68719476731, 1, 3),
+                                   (134217689, 1, 1)]):
+        m, n, k = 40 + 7 * i, 33 + 5 * i, 300 + 91 * i
+        A = gen.random_matrix(100 + i, 1, m, k, p)
+        B = gen.random_matrix(100 + i, 2, k, n, p)
+        C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+        jobs.append((dev(A), dev(B), C, p, u, v))
+        host.append((A, B, p))
+    say("centered batch", [(j[3], j[4], j[5]) for j in jobs])
+    mmp.mm_modp_batched(jobs, centered_words=True)
+    torch.cuda.synchronize()
+    for (A, B, p), j in zip(host, jobs):
+        assert_exact(j[2].cpu().numpy(), oracle.mm_modp(p, A, B))

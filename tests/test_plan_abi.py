@@ -190,6 +190,12 @@ def test_argument_errors_before_device_work():
     # (1,1) at 31 bits has no block size
     assert lib.mm_modp(2147483647, 1, 1, 4, 4, 4, fake, ctypes.c_void_p(0x9000),
                        ctypes.c_void_p(0x20000)) == -2
+    # a forced FP64 form whose A stage would span 2^31 bytes or more: refused on the host
+    big_a, big_b, big_c = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x7e0000000000), ctypes.c_void_p(0x7f0000000000)
+    assert lib.mm_modp_async(ctypes.byref(o), 33554393, 1, 1, 64, 64, 4, big_a, 1 << 28, big_b, 64,
+                             big_c, 64, None) == -1
+    assert lib.mm_modp_async(ctypes.byref(o), 33554393, 1, 1, 64, 64, 4, big_a, 4, big_b, 1 << 27,
+                             big_c, 64, None) == -1
     # empty products succeed without touching memory
     assert lib.mm_modp(33554393, 1, 1, 0, 4, 4, None, None, None) == 0
     assert lib.mm_modp(33554393, 1, 1, 4, 0, 4, None, None, None) == 0
@@ -569,3 +575,26 @@ def test_int8_fold_exact(p):
         for w in cases:
             want = sum(256 ** s * ws for s, ws in enumerate(w)) % p
             assert _fold_weights(w, p) == want
+
+
+@pytest.mark.parametrize("shape", [(512, 512, 131072), (16384, 16384, 256), (4096, 4096, 4096), (64, 64, 1 << 20),
+                                   (1000, 30, 50000)])
+@pytest.mark.parametrize("form", [1, 2])
+def test_split_policy(shape, form):
+    # k-ranges only when the output tiles cannot fill 256 CUs twice, a power of
+    # two (whole k-ranges per XCD from 8 on), each range at least 1024 (FP64)
+    # or 2048 (INT8) k-terms; the FP64 tile is the largest that reaches 512
+    # workgroups with them
+    m, n, k = shape
+    p = 8388593
+    pl = mmp.plan(p, m, n, k, form=form)
+    s_ = pl["splits"]
+    assert s_ >= 1 and s_ & (s_ - 1) == 0 and s_ <= 64
+    bm, bn = (pl["bm"], pl["bn"]) if form == 1 else (64, 64)
+    tiles = -(-m // bm) * -(-n // bn)
+    per = 1024 if form == 1 else 2048
+    if tiles >= 512:
+        assert s_ == 1
+    if s_ > 1:
+        assert k // s_ >= per and tiles * s_ // 2 < 512
+        assert pl["workspace_bytes"] >= 8 * s_ * m * n
