@@ -116,11 +116,13 @@ def test_every_forced_kblock(p, u, v):
 
 @pytest.mark.parametrize("tile", [1, 2, 3])
 def test_every_tile_shape(tile):
-    for p, (u, v) in [(33554393, (1, 1)), (34359738337, (1, 2)), (68719476731, (1, 3)),
+    # (1,1) at 20 and 23 bits reduce every 4 or more whole k-steps: the wide 128 x 128 tile
+    for p, (u, v) in [(33554393, (1, 1)), (1048573, (1, 1)), (8388593, (1, 1)), (34359738337, (1, 2)),
+                      (68719476731, (1, 3)),
                       (1125899906842597, (2, 2)), (1125899906842597, (2, 3)), (2147483647, (2, 4)),
                       (2147483647, (4, 2)), (2147483647, (3, 1)), (2147483647, (4, 1))]:
-        m, n, k = 150, 137, 77
-        say("tile", tile, p, u, v)
+        m, n, k = 150, 137, 77 if p != 8388593 else 300
+        say("tile", tile, p, u, v, mmp.plan(p, m, n, k, u, v, tile=tile)["bm"])
         A = gen.random_matrix(5, 1, m, k, p)
         B = gen.random_matrix(5, 2, k, n, p)
         assert_exact(run(p, A, B, u, v, tile=tile), oracle.mm_modp(p, A, B))
