@@ -2,14 +2,15 @@
 // per word pair by mmp_fp64_words.hip).
 //
 // One workgroup computes a BM x BN tile of C for all u v word pairs at once:
-//   1. prologue per LDS stage: coalesced global loads of an A (BM x KR) and a
-//      B (KR x BN) slab; every entry is split into words (Section 3.1, Alg. 4)
-//      on the way into LDS, so word planes never exist in HBM;
+//   1. per LDS stage (16 k-slots): buffer loads of an A (BM x KR) and a B
+//      (KR x BN) slab, issued a stage ahead into registers; every entry is
+//      split into words (Section 3.1, Alg. 4, or the centered variant) on the
+//      way into one of two LDS buffers, so word planes never exist in HBM;
 //   2. hot loop: for every word pair (i, j), 16x16x4 FP64 MFMAs accumulate
 //      A_i B_j into VGPR accumulators; after each k-block of at most the
-//      paper's block size (Section 2.2, Prop. blockProduct; Section 3.2,
-//      Prop. UVMW) every accumulator is reduced mod p with the fma-based
-//      reduction (Section 2.1, Alg. 1);
+//      block size (the paper's: Section 2.2, Prop. blockProduct; Section 3.2,
+//      Prop. UVMW; or an opt-in bound) every accumulator is reduced mod p
+//      with the fma-based reduction (Section 2.1, Alg. 1);
 //   3. epilogue: a complete reduction, then the word products are recombined
 //      as sum_i alpha^i sum_j beta^j T_ij mod p by Horner's rule, each step a
 //      modular product by alpha or beta (Section 2.1, Alg. 2) and a modular

@@ -77,10 +77,10 @@ int64_t extended_lambda(uint64_t p, int u, int v) {
 // Centered words (a variant of Alg. 4 derived for this library).  An entry
 // x in [0, p) becomes x~ = x - p when 2x > p, so |x~| <= h = floor(p / 2),
 // and is split as x~ = sum_i alpha^i w_i with quotients rounded to nearest:
-// r = rint(t / alpha) (exact when alpha is a power of two, else a correctly
-// rounded division), w = t - r alpha.  Then |w| <= alpha / 2 + |t| 2^-53 <
-// alpha / 2 + 1 for every word but the last, and the last, the final
-// quotient, is at most h / alpha^(u-1) + 2.
+// r = floor(fl(t fl(1/alpha) + 1/2)), w = t - r alpha.  The estimate is
+// within |t / alpha| 2^-52 of t / alpha, so |w| <= alpha / 2 + |t| 2^-52 <
+// alpha / 2 + 1 for every word but the last (|t| < 2^51), and the last, the
+// final quotient, is at most h / alpha^(u-1) + 2.
 uint64_t centered_word_bound(uint64_t p, int u) {
   const uint64_t h = p / 2;
   if (u <= 1) return h;
