@@ -259,7 +259,8 @@ int mmp_server_destroy(mmp_server *srv);
  * registers an A operand (rows x cols = m x k), side 1 a B operand (k x n),
  * for modulus p.  A later request whose A (or B) has this pointer, shape,
  * leading dimension and modulus skips digitising it (the paper's setting of
- * a fixed A reused across products, Section 4.1).  The planes count against
+ * a fixed A reused across products, Section 4.1); an AUTO request (u = v =
+ * 0) with a resident operand takes the INT8 form.  The planes count against
  * the budget until mmp_unregister_operand.  The matrix must not change while
  * registered.  Synchronous. */
 int mmp_register_operand(mmp_server *srv, const double *M, int64_t rows,

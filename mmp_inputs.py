@@ -208,6 +208,14 @@ def config_problems(index: int) -> list[Problem]:
     raise ValueError("config index 1..4 are single products; use crt_job() / serve_stream()")
 
 
+def unbalanced_problem(bits: int) -> Problem:
+    """The paper's second workload (Section 4.1): m = 10923, k = 32768, n = 32,
+    the iterated product of block-Wiedemann; uniform entries at the largest
+    prime below 2^bits."""
+    return Problem(10923, 32, 32768, largest_prime_below_pow2(bits), BASE_SEED + 7,
+                   tag=f"unbal10923x32768x32_b{bits}")
+
+
 @dataclass
 class CrtJob:
     """One integer pair A, B (entries < 2^bits) reduced against many primes."""

@@ -36,7 +36,7 @@ struct Fp64Tile {
 // 4 x 4 tiles.
 constexpr Fp64Tile fp64_tile_c(int tile_id, int u, int v, bool wide) {
   if (tile_id == 3) return Fp64Tile{1, 1};
-  if (tile_id == 2) return u * v <= 2 ? Fp64Tile{2, 2} : u * v <= 4 ? Fp64Tile{1, 2} : Fp64Tile{1, 1};
+  if (tile_id == 2) return Fp64Tile{2, 1};  // 64 x 32: narrow outputs (n <= 32) and mid-size products
   if (u == 1 && v == 1) return wide ? Fp64Tile{4, 4} : Fp64Tile{4, 2};
   if (u * v == 2) return u < v ? Fp64Tile{4, 2} : Fp64Tile{2, 4};
   if (u == 1 && v == 4) return Fp64Tile{4, 1};

@@ -196,15 +196,25 @@ double int8_seconds(int64_t m, int64_t n, int64_t k, int d) {
   return gemm + digitize + fold + 3 * 4e-6;
 }
 
-// The largest tile that fills the chip (two workgroups per CU), counting
-// the k-ranges split-K adds for long k; else the smallest.
+// Among the tiles that fill the chip (two workgroups per CU, counting the
+// k-ranges split-K adds for long k), the one with the least padded output
+// area, the larger on a tie (a 128-wide tile on n = 32 would compute 75%
+// padding); if none fills the chip, the smallest.
 int pick_tile(int u, int v, int64_t m, int64_t n, int64_t stages, int slots, int64_t kblock) {
+  int best = 0;
+  int64_t best_area = 0;
   for (int id = 1; id <= 3; id++) {
     Fp64Tile t = fp64_tile(id, u, v, slots, kblock);
-    int64_t nb = cdiv(m, fp64_bm(t)) * cdiv(n, fp64_bn(t));
-    if (nb * choose_splits(nb, stages, 64) >= 512) return id;
+    const int64_t bm = fp64_bm(t), bn = fp64_bn(t);
+    const int64_t nb = cdiv(m, bm) * cdiv(n, bn);
+    if (nb * choose_splits(nb, stages, 64) < 512) continue;
+    const int64_t area = cdiv(m, bm) * bm * cdiv(n, bn) * bn;
+    if (best == 0 || area < best_area) {
+      best = id;
+      best_area = area;
+    }
   }
-  return 3;
+  return best ? best : 3;
 }
 
 // ---------------------------------------------------------------- tuning cache

@@ -409,6 +409,20 @@ int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
       if (int st = mmp::plan(j.p, 0, 0, j.m, j.n, j.k, &o1, &r.plan)) return st;
     }
     std::lock_guard<std::mutex> lk(s->mu);
+    // An AUTO request with an operand whose digit planes are resident takes
+    // the INT8 form: the planner's estimate charges for digitising both
+    // operands, which a resident operand no longer needs.
+    if (r.plan.form == MMP_FORM_FP64_WORDS && j.u == 0 && j.m > 0 && j.n > 0 && j.k > 0) {
+      mmp_opts o8 = o1;
+      o8.form = MMP_FORM_INT8_WORDS;
+      mmp_plan_t p8;
+      if (mmp::plan(j.p, 0, 0, j.m, j.n, j.k, &o8, &p8) == MMP_OK) {
+        const int64_t kp = (j.k + 63) / 64 * 64;
+        if (s->find_resident(j.A, j.m, j.k, j.lda, j.p, 0, p8.digits_a, kp) ||
+            s->find_resident(j.B, j.k, j.n, j.ldb, j.p, 1, p8.digits_b, kp))
+          r.plan = p8;
+      }
+    }
     if (r.plan.form == MMP_FORM_INT8_WORDS) {
       const int64_t kp = (j.k + 63) / 64 * 64;
       r.res_a = s->find_resident(j.A, j.m, j.k, j.lda, j.p, 0, r.plan.digits_a, kp);

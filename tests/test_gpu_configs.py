@@ -119,3 +119,26 @@ def test_crt_2048_32_primes():
         want = oracle.mm_modp_entries(p, A, B, rr, cc).astype(np.float64)
         got = C[torch.from_numpy(rr).cuda(), torch.from_numpy(cc).cuda()].cpu().numpy()
         assert np.array_equal(got, want), p
+
+
+@pytest.mark.parametrize("bits", [26, 50])
+def test_unbalanced_10923x32768x32(bits):
+    # the paper's second workload: both forms and the server with A resident
+    prob = gen.unbalanced_problem(bits)
+    A, B = prob.a(), prob.b()
+    dA = torch.from_numpy(A.astype(np.float64)).cuda()
+    dB = torch.from_numpy(B.astype(np.float64)).cuda()
+    outs = []
+    for form in (1, 2):
+        C = torch.full((prob.m, prob.n), -1.0, dtype=torch.float64, device="cuda")
+        say("unbalanced", bits, "form", form, mmp.plan(prob.p, prob.m, prob.n, prob.k, form=form))
+        mmp.mm_modp_async(dA, dB, C, prob.p, form=form)
+        outs.append(C)
+    C = torch.full((prob.m, prob.n), -1.0, dtype=torch.float64, device="cuda")
+    with mmp.Server(hbm_budget=32 << 30, max_slots=4) as srv:
+        srv.register_operand(dA, prob.p, 0)
+        assert srv.wait(srv.submit(dA, dB, C, prob.p), 120.0)[0] == 0
+    outs.append(C)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    _check_sampled(prob, A, B, outs[0], nrows=2, ncols=1, nrand=256)

@@ -119,3 +119,28 @@ def test_resident_operand_reused():
             assert np.array_equal(C.cpu().numpy(), oracle.mm_modp(p, A, B).astype(np.float64))
         srv.unregister_operand(h)
         assert srv.stats()["resident_bytes"] == 0
+
+
+def test_resident_operand_switches_auto_to_int8_form():
+    # at 26 bits the planner alone picks FP64 words for this narrow shape (it
+    # charges digitising A); with A resident the request runs in the INT8 form
+    p = 67108859
+    m, n, k = 1000, 32, 8192
+    assert mmp.plan(p, m, n, k)["form"] == 1
+    A = gen.random_matrix(41, 1, m, k, p)
+    B = gen.random_matrix(41, 2, k, n, p)
+    dA, dB = dev(A), dev(B)
+    C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+    with mmp.Server(hbm_budget=4 << 30, max_slots=4) as srv:
+        srv.register_operand(dA, p, 0)
+        mmp.timers_read(reset=True)
+        mmp.timers_enable(True)
+        assert srv.wait(srv.submit(dA, dB, C, p), 60.0)[0] == 0
+        torch.cuda.synchronize()
+        mmp.timers_enable(False)
+        t = mmp.timers_read(reset=True)
+    say("timers", t)
+    assert t.get("int8_gemm", (0, 0))[0] == 1 and t.get("int8_digitize_a", (0, 0))[0] == 0
+    assert "fp64_words" not in t or t["fp64_words"][0] == 0
+    want = oracle.mm_modp(p, A, B).astype(np.float64)
+    assert np.array_equal(C.cpu().numpy(), want)
