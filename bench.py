@@ -127,7 +127,7 @@ def serving(mmp, torch, gen, count, loads):
                     if arrivals is not None:
                         while time.perf_counter() - t0 < arrivals[i]:
                             time.sleep(0)
-                    tickets[i] = srv.submit(A, B, C, pr.p)
+                    tickets[i] = srv.submit(A, B, C, pr.p, wait_caller=False)  # inputs synchronised above
 
             th = threading.Thread(target=submitter)
             th.start()

@@ -262,7 +262,8 @@ int mmp_server_destroy(mmp_server *srv);
  * a fixed A reused across products, Section 4.1); an AUTO request (u = v =
  * 0) with a resident operand takes the INT8 form.  The planes count against
  * the budget until mmp_unregister_operand.  The matrix must not change while
- * registered.  Synchronous. */
+ * registered, and device work that writes it must have completed before
+ * this call.  Synchronous. */
 int mmp_register_operand(mmp_server *srv, const double *M, int64_t rows,
                          int64_t cols, int64_t ld, uint64_t p, int side,
                          uint64_t *handle);
@@ -273,7 +274,11 @@ int mmp_unregister_operand(mmp_server *srv, uint64_t handle);
 /* Queues one product (non-blocking); *ticket identifies it.  MMP_ENOMEM if
  * its footprint can never fit the budget; with MMP_SUBMIT_NOQUEUE,
  * MMP_EBUSY when it cannot be admitted immediately.  The job's buffers must
- * stay valid until the ticket is reported done. */
+ * stay valid until the ticket is reported done.  The server's streams are
+ * not ordered after any caller stream: device work that writes A, B or C
+ * must have completed before mmp_submit is called (e.g. by synchronising
+ * the stream that ran it), and C must not be touched until the ticket is
+ * reported done. */
 int mmp_submit(mmp_server *srv, const mmp_job *job, int flags,
                uint64_t *ticket);
 

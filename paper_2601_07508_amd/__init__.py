@@ -355,6 +355,11 @@ class Server:
 
     Tensors passed to submit() are kept referenced until their ticket is
     reported done, so their memory cannot be released while in flight.
+    The server's streams are not ordered after the caller's: register_operand()
+    and submit() first wait for torch's current stream, so that work queued
+    there to produce A, B or C has finished before the server reads or
+    writes them (submit(..., wait_caller=False) skips the wait when the
+    caller has already synchronised).
     """
 
     def __init__(self, hbm_budget: int, max_slots: int = 64, device: int = 0, dry_run: bool = False):
@@ -375,8 +380,13 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
+    def _wait_caller(self, t):
+        import torch
+        torch.cuda.current_stream(t.device).synchronize()
+
     def register_operand(self, M, p: int, side: int) -> int:
         _check_mat(M, "M")
+        self._wait_caller(M)
         h = _u64()
         _check(_lib.mmp_register_operand(self._h, M.data_ptr(), M.shape[0], M.shape[1], max(M.stride(0), 1),
                                          p, side, ctypes.byref(h)), "mmp_register_operand")
@@ -395,8 +405,11 @@ class Server:
             self._keep[t.value] = keep
         return t.value
 
-    def submit(self, A, B, C, p: int, u: int = 0, v: int = 0, noqueue: bool = False) -> int:
+    def submit(self, A, B, C, p: int, u: int = 0, v: int = 0, noqueue: bool = False,
+               wait_caller: bool = True) -> int:
         arr = _jobs_array([(A, B, C, p, u, v)])
+        if wait_caller:
+            self._wait_caller(C)
         return self.submit_raw(arr[0], noqueue, keep=(A, B, C))
 
     def poll(self, ticket: int):
