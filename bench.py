@@ -187,8 +187,9 @@ def bench_unbalanced(args, mmp, torch, gen):
     across the iterations of block-Wiedemann, B new each time.  Per bitsize:
     the FP64 words (A's words are formed inside the kernel on every call), the
     INT8 digits with A digitised on every call, and the INT8 digits with A's
-    digit planes resident in a server (only B digitised per call, the paper's
-    timing rule for this workload).  Outputs of all three must agree."""
+    digit planes prepared once (only B digitised per call, the paper's timing
+    rule for this workload), directly and through a server with A registered.
+    Outputs of all must agree."""
     import numpy as np
 
     for b in [int(x) for x in args.unbalanced.split(",")]:
@@ -206,7 +207,16 @@ def bench_unbalanced(args, mmp, torch, gen):
                          "uv": [pl["u"], pl["v"]], "digits": pl["digits_a"], "tile": [pl["bm"], pl["bn"]],
                          "splits": pl["splits"]}
             outs[name] = C
-        # A resident: requests submitted back to back, each waited for
+        # A's digit planes prepared once (not timed, as in the paper); each
+        # call digitises B, multiplies and reduces
+        C = torch.empty((m, n), dtype=torch.float64, device="cuda")
+        pa = mmp.prepare_operand(dA, p, 0)
+        ms = _time(torch, lambda: mmp.mm_modp_async(dA, dB, C, p, stream=stream, prepared_a=pa), 2, args.steps)
+        res["int8_digits_prepared_a"] = {"ms": round(ms, 4), "eff_gflops": round(2.0 * m * n * k / ms / 1e6, 1)}
+        outs["int8_digits_prepared_a"] = C
+        del pa
+        # the same through the server with A registered: requests submitted
+        # back to back, each waited for (adds the server's host round trip)
         C = torch.empty((m, n), dtype=torch.float64, device="cuda")
         with mmp.Server(hbm_budget=64 << 30, max_slots=4) as srv:
             srv.register_operand(dA, p, 0)
@@ -217,13 +227,15 @@ def bench_unbalanced(args, mmp, torch, gen):
             for _ in range(args.steps):
                 srv.wait(srv.submit(dA, dB, C, p), 60.0)
             ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        res["int8_digits_resident_a"] = {"ms": round(ms, 4), "eff_gflops": round(2.0 * m * n * k / ms / 1e6, 1)}
-        outs["int8_digits_resident_a"] = C
+        res["int8_digits_server_resident_a"] = {"ms": round(ms, 4),
+                                                "eff_gflops": round(2.0 * m * n * k / ms / 1e6, 1)}
+        outs["int8_digits_server_resident_a"] = C
         same = all(torch.equal(outs["fp64_words"], c) for c in outs.values())
         ok = all(_residues_ok(torch, c, p) for c in outs.values())
         print(json.dumps({"workload": prob.tag, "bits": b, "p": p, "shape": [m, n, k], "forms": res,
                           "identical_outputs": bool(same), "residues_in_range": ok,
-                          "note": "resident-A time is per request through the server (submit to completion)"}),
+                          "note": "prepared-A: A's digit planes made once, untimed; server: per request, "
+                                  "submit to completion"}),
               flush=True)
         del dA, dB, outs
         torch.cuda.empty_cache()

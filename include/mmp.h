@@ -67,6 +67,20 @@ enum {
                                accumulation, binary64 reduction/recombination */
 };
 
+/* The INT8 digit planes of one operand, made once by mmp_prepare_operand and
+ * reused by INT8-form products: the fixed A of the unbalanced block-Wiedemann
+ * benchmark of Section 4.1, whose decomposition the paper times apart from
+ * the products.  Filled by the library; the caller owns the planes' memory. */
+typedef struct {
+  const int8_t *planes;   /* device; [digits][outer][kp] signed base-256
+                             digits (outer = rows of an A, cols of a B) */
+  uint64_t p;             /* the modulus the entries were reduced for */
+  int side;               /* 0: an A (rows x cols = m x k); 1: a B (k x n) */
+  int digits;             /* ceil(bits(p) / 8) */
+  int64_t rows, cols;     /* the shape of the matrix they were made from */
+  int64_t kp;             /* inner dimension rounded up to a multiple of 64 */
+} mmp_operand_t;
+
 /* Options; a NULL mmp_opts* means all fields zero. */
 typedef struct {
   int form;               /* MMP_FORM_* */
@@ -113,6 +127,14 @@ typedef struct {
                              word bounds).  Exclusive with extended_block and
                              strict_fmod.  0: the paper's words. */
   int reserved[1];        /* must be zero */
+  const mmp_operand_t *prepared_a; /* mm_modp_async only: A's digit planes
+                             from mmp_prepare_operand (same p and shape);
+                             the product then takes the
+                             INT8 form and reads the planes instead of
+                             digitising A (A itself is not read).  NULL:
+                             none.  Other entry points return MMP_EINVAL
+                             when it is set. */
+  const mmp_operand_t *prepared_b; /* the same for B */
 } mmp_opts;
 
 /* What the planner decided for one product (mmp_plan fills it). */
@@ -176,6 +198,24 @@ int mm_modp_async(const mmp_opts *opts, uint64_t p, int u, int v, int64_t m,
                   int64_t n, int64_t k, const double *A, int64_t lda,
                   const double *B, int64_t ldb, double *C, int64_t ldc,
                   void *stream);
+
+/* Device bytes of one operand's digit planes (0 for invalid arguments):
+ * digits x outer x kp, with outer = rows of an A (side 0) or cols of a B
+ * (side 1) and kp the inner dimension rounded up to 64. */
+size_t mmp_operand_bytes(uint64_t p, int side, int64_t rows, int64_t cols);
+
+/* Writes the signed base-256 digit planes of M (entries in [0, p), row
+ * stride ld) into the caller's device buffer `planes` (at least
+ * mmp_operand_bytes) on `stream`, and fills *out to describe them; pass
+ * out through mmp_opts.prepared_a (side 0) or prepared_b (side 1).  The
+ * digits are those the INT8 form makes per call (the multiword split of
+ * Section 3.1 with 8-bit words, the low-precision words of Section 6).
+ * Asynchronous; `planes` must stay valid and unchanged while products use
+ * it.  MMP_EINVAL for bad arguments or a buffer too small. */
+int mmp_prepare_operand(uint64_t p, int side, const double *M, int64_t rows,
+                        int64_t cols, int64_t ld, void *planes,
+                        size_t planes_bytes, mmp_operand_t *out,
+                        void *stream);
 
 /* ---------------------------------------------------------------- batches */
 

@@ -33,10 +33,16 @@ STATUS = {0: "MMP_OK", -1: "MMP_EINVAL", -2: "MMP_EBOUND", -3: "MMP_ERANGE", -4:
           -5: "MMP_EHIP", -6: "MMP_EBUSY", -7: "MMP_ENOTFOUND", -8: "MMP_ETIMEOUT"}
 
 
+class MmpOperand(ctypes.Structure):
+    _fields_ = [("planes", _vp), ("p", _u64), ("side", _int), ("digits", _int), ("rows", _i64), ("cols", _i64),
+                ("kp", _i64)]
+
+
 class MmpOpts(ctypes.Structure):
     _fields_ = [("form", _int), ("validate_entries", _int), ("tile", _int), ("strict_fmod", _int),
                 ("force_kblock", _i64), ("workspace", _vp), ("workspace_bytes", _sz), ("extended_block", _int),
-                ("splits", _int), ("centered_words", _int), ("reserved", _int * 1)]
+                ("splits", _int), ("centered_words", _int), ("reserved", _int * 1),
+                ("prepared_a", ctypes.POINTER(MmpOperand)), ("prepared_b", ctypes.POINTER(MmpOperand))]
 
 
 class MmpPlan(ctypes.Structure):
@@ -143,8 +149,13 @@ def strerror(status: int) -> str:
 
 
 def _opts(form=FORM_AUTO, force_kblock=0, validate_entries=False, tile=0, strict_fmod=False,
-          workspace=None, extended_block=False, splits=0, centered_words=False):
+          workspace=None, extended_block=False, splits=0, centered_words=False, prepared_a=None,
+          prepared_b=None):
     o = MmpOpts()
+    if prepared_a is not None:  # a PreparedOperand (its struct lives as long as it does)
+        o.prepared_a = ctypes.pointer(prepared_a.desc)
+    if prepared_b is not None:
+        o.prepared_b = ctypes.pointer(prepared_b.desc)
     o.splits = splits
     o.extended_block = 1 if extended_block else 0
     o.centered_words = 1 if centered_words else 0
@@ -229,6 +240,31 @@ def mm_modp_async(A, B, C, p: int, u: int = 0, v: int = 0, stream=None, **opts):
                             _stream_ptr(stream))
     _check(st, "mm_modp_async")
     return C
+
+
+class PreparedOperand:
+    """The INT8 digit planes of one operand (see mmp_prepare_operand); pass it
+    as ``prepared_a=`` / ``prepared_b=`` to mm_modp_async.  Holds the planes'
+    device memory and the matrix it was made from."""
+
+    def __init__(self, M, p: int, side: int, stream=None):
+        import torch
+        _check_mat(M, "M")
+        rows, cols = M.shape
+        nbytes = _lib.mmp_operand_bytes(p, side, rows, cols)
+        if nbytes == 0:
+            raise MmpError(-1, "mmp_operand_bytes")
+        self.planes = torch.empty(nbytes, dtype=torch.int8, device=M.device)
+        self.source = M
+        self.desc = MmpOperand()
+        _check(_lib.mmp_prepare_operand(p, side, M.data_ptr(), rows, cols, max(M.stride(0), 1),
+                                        self.planes.data_ptr(), nbytes, ctypes.byref(self.desc),
+                                        _stream_ptr(stream)), "mmp_prepare_operand")
+
+
+def prepare_operand(M, p: int, side: int, stream=None) -> PreparedOperand:
+    """Digit planes of M (side 0: an A, side 1: a B) for reuse across products."""
+    return PreparedOperand(M, p, side, stream)
 
 
 def mm_modp(A, B, p: int, u: int = 0, v: int = 0, out=None, stream=None, **opts):
@@ -338,6 +374,10 @@ _lib.mmp_server_destroy.argtypes = [_vp]
 _lib.mmp_server_destroy.restype = _int
 _lib.mmp_register_operand.argtypes = [_vp, _vp, _i64, _i64, _i64, _u64, _int, ctypes.POINTER(_u64)]
 _lib.mmp_register_operand.restype = _int
+_lib.mmp_operand_bytes.argtypes = [_u64, _int, _i64, _i64]
+_lib.mmp_operand_bytes.restype = _sz
+_lib.mmp_prepare_operand.argtypes = [_u64, _int, _vp, _i64, _i64, _i64, _vp, _sz, ctypes.POINTER(MmpOperand), _vp]
+_lib.mmp_prepare_operand.restype = _int
 _lib.mmp_unregister_operand.argtypes = [_vp, _u64]
 _lib.mmp_unregister_operand.restype = _int
 _lib.mmp_submit.argtypes = [_vp, ctypes.POINTER(MmpJob), _int, ctypes.POINTER(_u64)]

@@ -77,6 +77,14 @@ int check_product_args(int64_t m, int64_t n, int64_t k, const double* A, int64_t
   return MMP_OK;
 }
 
+// Prepared planes describe the operand a product reads: same side, modulus,
+// shape and digit count.
+bool operand_fits(const mmp_operand_t& o, int side, uint64_t p, int64_t rows, int64_t cols, int digits) {
+  const int64_t inner = side == 0 ? cols : rows;
+  return o.planes && o.side == side && o.p == p && o.rows == rows && o.cols == cols && o.digits == digits &&
+         o.kp == (inner + 63) / 64 * 64;
+}
+
 // Stream-ordered workspace: the device's default memory pool, told to keep
 // freed blocks cached so repeated calls do not return memory to the driver.
 static std::mutex g_pool_mu;
@@ -265,8 +273,24 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
                   void* stream) {
   try {
     if (int st = check_product_args(m, n, k, A, lda, B, ldb, C, ldc)) return st;
+    const mmp_operand_t* pa = opts ? opts->prepared_a : nullptr;
+    const mmp_operand_t* pb = opts ? opts->prepared_b : nullptr;
     mmp_plan_t pl;
-    if (int st = mmp::plan(p, u, v, m, n, k, opts, &pl)) return st;
+    if (pa || pb) {
+      // prepared digit planes: the INT8 form, planned without them
+      if (u != 0 || opts->form == MMP_FORM_FP64_WORDS || opts->tile || opts->extended_block ||
+          opts->centered_words)
+        return MMP_EINVAL;
+      mmp_opts o2 = *opts;
+      o2.form = MMP_FORM_INT8_WORDS;
+      o2.prepared_a = nullptr;
+      o2.prepared_b = nullptr;
+      if (int st = mmp::plan(p, 0, 0, m, n, k, &o2, &pl)) return st;
+      if (pa && !operand_fits(*pa, 0, p, m, k, pl.digits_a)) return MMP_EINVAL;
+      if (pb && !operand_fits(*pb, 1, p, k, n, pl.digits_b)) return MMP_EINVAL;
+    } else if (int st = mmp::plan(p, u, v, m, n, k, opts, &pl)) {
+      return st;
+    }
     if (!fp64_ld_ok(pl, lda, ldb)) {
       // leading dimensions beyond the FP64 kernel's offsets: an AUTO plan
       // takes the INT8 form, which has no such limit; a forced one fails
@@ -284,16 +308,20 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
     if (opts && opts->validate_entries)
       if (int st = validate_product_entries(p, m, n, k, A, lda, B, ldb, stream)) return st;
 
+    // split-K residues go after the digit planes made per call (INT8) or
+    // fill the workspace (FP64)
+    const size_t planes = pl.form == MMP_FORM_INT8_WORDS
+                              ? int8_planes_bytes(pl.digits_a, m, n, k, pa != nullptr, pb != nullptr) : 0;
+    const size_t need = planes + (pl.splits > 1 ? 8 * (size_t)pl.splits * (size_t)m * (size_t)n : 0);
     void* work = nullptr;
     bool owned = false;
-    if (int st = acquire_workspace(pl.workspace_bytes, opts, stream, &work, &owned)) return st;
-    // split-K residues go after the digit planes (INT8) or fill the workspace (FP64)
-    const size_t planes = pl.form == MMP_FORM_INT8_WORDS
-                              ? (int8_workspace_bytes(pl.digits_a, m, n, k) + 255) / 256 * 256 : 0;
+    if (int st = acquire_workspace(need, opts, stream, &work, &owned)) return st;
     double* partial = pl.splits > 1 ? (double*)((char*)work + planes) : nullptr;
     int e;
     if (pl.form == MMP_FORM_INT8_WORDS) {
       Int8Args g = make_int8_args(pl, m, n, k, A, lda, B, ldb, C, ldc, (int8_t*)work);
+      g.resident_a = pa ? pa->planes : nullptr;
+      g.resident_b = pb ? pb->planes : nullptr;
       g.splits = pl.splits;
       g.partial = partial;
       e = launch_int8_digitize(pl.digits_a, g, stream);
@@ -311,6 +339,36 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
     const int st = hip_status(e);
     const int st2 = release_workspace(work, owned, stream);
     return st ? st : st2;
+  } catch (...) {
+    return MMP_EINVAL;
+  }
+}
+
+size_t mmp_operand_bytes(uint64_t p, int side, int64_t rows, int64_t cols) {
+  if (p < 5 || p >= kPMax || (side != 0 && side != 1) || rows <= 0 || cols <= 0) return 0;
+  const int64_t inner = side == 0 ? cols : rows, outer = side == 0 ? rows : cols;
+  return (size_t)digits_for(p) * (size_t)outer * (size_t)((inner + 63) / 64 * 64);
+}
+
+int mmp_prepare_operand(uint64_t p, int side, const double* M, int64_t rows, int64_t cols, int64_t ld,
+                        void* planes, size_t planes_bytes, mmp_operand_t* out, void* stream) {
+  try {
+    const size_t need = mmp_operand_bytes(p, side, rows, cols);
+    if (!out || !M || !planes || need == 0 || ld < cols || planes_bytes < need) return MMP_EINVAL;
+    const int64_t inner = side == 0 ? cols : rows;
+    mmp_operand_t o;
+    std::memset(&o, 0, sizeof(o));
+    o.planes = (const int8_t*)planes;
+    o.p = p;
+    o.side = side;
+    o.digits = digits_for(p);
+    o.rows = rows;
+    o.cols = cols;
+    o.kp = (inner + 63) / 64 * 64;
+    if (int e = launch_int8_digitize_side(o.digits, side, M, rows, cols, ld, o.kp, p, (int8_t*)planes, stream))
+      return hip_status(e);
+    *out = o;
+    return MMP_OK;
   } catch (...) {
     return MMP_EINVAL;
   }

@@ -181,6 +181,7 @@ int mm_modp_crt(const mmp_opts* opts, const uint64_t* A, int64_t lda, const uint
     if (opts) {
       for (int r : opts->reserved)
         if (r != 0) return MMP_EINVAL;
+      if (opts->prepared_a || opts->prepared_b) return MMP_EINVAL;
     }
     for (int i = 0; i < nprimes; i++) {
       if (primes[i] < 5 || primes[i] >= kPMax) return MMP_EINVAL;

@@ -120,6 +120,7 @@ struct Int8Args {
   int8_t* work;      // D (m + n) kp bytes: planes of A, then of B^T
   const int8_t* resident_a;  // optional ready planes of A (then A is not digitised)
   const int8_t* resident_b;  // optional ready planes of B^T
+  // work holds the planes made per call: A's (absent when resident), then B's
   int splits;                // split-K: k-ranges (1: none)
   double* partial;           // splits > 1: residues per k-range, [splits][m][n]
 };
@@ -128,6 +129,8 @@ int launch_splitk_reduce(const double* partial, int splits, int64_t m, int64_t n
                          void* stream);
 // Split count for a product of `tiles` output tiles and `stages` k-stages.
 int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split);
+// the planner's split-K for a plan (its form, tile and block) and shape
+int default_splits(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k);
 // Digit planes of one operand side into out (side 0: A rows -> [D][rows][kp];
 // side 1: B columns -> [D][cols][kp]).
 int launch_int8_digitize_side(int digits, int side, const double* X, int64_t rows, int64_t cols, int64_t ld,
@@ -135,6 +138,8 @@ int launch_int8_digitize_side(int digits, int side, const double* X, int64_t row
 int digits_for(uint64_t p);                       // ceil(bitsize(p) / 8)
 int64_t int8_kblock(int digits);                  // exact-int32 block length
 size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k);
+// planes made per call when A and/or B are resident (rounded up to 256 bytes)
+size_t int8_planes_bytes(int digits, int64_t m, int64_t n, int64_t k, bool res_a, bool res_b);
 // Multi-modular product of one integer pair (uint64 entries < 2^entry_bits)
 // against up to kMaxPrimesCrt moduli, all from one digit GEMM; needs
 // k <= int8_kblock(digits).

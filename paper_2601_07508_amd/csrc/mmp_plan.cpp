@@ -304,6 +304,13 @@ int digits_for(uint64_t p) {
   return (bits + 7) / 8;
 }
 
+int default_splits(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k) {
+  if (pl.form == MMP_FORM_INT8_WORDS) return choose_splits(cdiv(m, 64) * cdiv(n, 64), cdiv(k, 64), 32);
+  // real k-terms per 16-slot stage: fewer only when blocks leave zero slots
+  const int64_t KR = (pl.slots <= kBK && pl.kblock < pl.slots) ? (kBK / pl.slots) * pl.kblock : kBK;
+  return choose_splits(cdiv(m, pl.bm) * cdiv(n, pl.bn), cdiv(k, KR), 64);
+}
+
 int64_t int8_kblock(int digits) {
   // K min(D_A, D_B) 2^14 <= 2^31 - 1 keeps every int32 accumulator exact
   const int64_t K = ((int64_t)1 << 31) - 1;
@@ -316,6 +323,12 @@ size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k) {
   return (size_t)digits * (size_t)(m + n) * (size_t)kp;
 }
 
+size_t int8_planes_bytes(int digits, int64_t m, int64_t n, int64_t k, bool res_a, bool res_b) {
+  const size_t kp = (size_t)(cdiv(k, 64) * 64);
+  const size_t rows = (res_a ? 0 : (size_t)m) + (res_b ? 0 : (size_t)n);
+  return ((size_t)digits * rows * kp + 255) / 256 * 256;
+}
+
 static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,
                      mmp_plan_t* out, bool use_tuned) {
   if (!out) return MMP_EINVAL;
@@ -323,9 +336,12 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   mmp_opts o;
   std::memset(&o, 0, sizeof(o));
   if (opts) o = *opts;
-  if (opts)
+  if (opts) {
     for (int r : opts->reserved)
       if (r != 0) return MMP_EINVAL;
+    // prepared operands are taken by mm_modp_async alone, which plans without them
+    if (opts->prepared_a || opts->prepared_b) return MMP_EINVAL;
+  }
   if (p < 5 || p >= kPMax) return MMP_EINVAL;
   if (m < 0 || n < 0 || k < 0) return MMP_EINVAL;
   if ((u == 0) != (v == 0)) return MMP_EINVAL;
@@ -355,8 +371,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     out->q = 1.0 / (double)p;
     out->bk = 64;
     out->est_seconds = int8_seconds(m, n, k, d8);
-    const int64_t tiles = cdiv(m, 64) * cdiv(n, 64);
-    out->splits = o.splits ? o.splits : choose_splits(tiles, cdiv(k, 64), 32);
+    out->splits = o.splits ? o.splits : default_splits(*out, m, n, k);
     out->workspace_bytes = (int8_workspace_bytes(d8, m, n, k) + 255) / 256 * 256;
     if (out->splits > 1) out->workspace_bytes += 8 * (size_t)out->splits * (size_t)m * (size_t)n;
     return MMP_OK;
@@ -454,11 +469,8 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->bk = kBK;
   out->q = 1.0 / (double)p;
   out->est_seconds = fp64_seconds(m, n, k, bu * bv, bk.cost);
-  {
-    const int64_t tiles = cdiv(m, out->bm) * cdiv(n, out->bn);
-    out->splits = o.splits ? o.splits : choose_splits(tiles, cdiv(k, KR), 64);
-    out->workspace_bytes = out->splits > 1 ? 8 * (size_t)out->splits * (size_t)m * (size_t)n : 0;
-  }
+  out->splits = o.splits ? o.splits : default_splits(*out, m, n, k);
+  out->workspace_bytes = out->splits > 1 ? 8 * (size_t)out->splits * (size_t)m * (size_t)n : 0;
   if (o.form == MMP_FORM_AUTO && u == 0 && o.force_kblock == 0 && o.tile == 0 && !extended && !centered &&
       int8_seconds(m, n, k, d8) < out->est_seconds) {
     std::memset(out, 0, sizeof(*out));

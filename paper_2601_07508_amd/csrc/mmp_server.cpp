@@ -61,6 +61,7 @@ struct Request {
   int state = 0;  // 0 queued, 1 running, 2 done
   const Operand* res_a = nullptr;
   const Operand* res_b = nullptr;
+  int solo_splits = 1;  // split-K when launched alone (the planner's choice)
 };
 
 struct InFlight {
@@ -114,6 +115,7 @@ struct mmp_server {
       if (r.res_a) fp -= (size_t)r.plan.digits_a * (size_t)(r.job.m * r.job.k);
       if (r.res_b) fp -= (size_t)r.plan.digits_b * (size_t)(r.job.k * r.job.n);
     }
+    if (r.solo_splits > 1) fp += 8 * (size_t)r.solo_splits * (size_t)(r.job.m * r.job.n);  // k-range residues
     return fp;
   }
 
@@ -142,7 +144,7 @@ struct mmp_server {
         if (g.stream == s) start = std::max(start, g.sim_end);
       f.sim_end = start + est;
     } else {
-      int err = run_requests_locked(batch, streams[s]);
+      int err = run_requests_locked(batch, streams[s], inflight.empty());
       if (!err) err = (int)hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
       if (!err) err = (int)hipEventRecord(f.ev, streams[s]);
       if (err) {
@@ -158,18 +160,35 @@ struct mmp_server {
 
   // Enqueues the batch on stream s; returns a hipError_t (> 0) or a
   // negative mmp_status.
-  int run_requests_locked(const std::vector<uint64_t>& batch, hipStream_t s) {
+  int run_requests_locked(const std::vector<uint64_t>& batch, hipStream_t s, bool idle) {
     // FP64-word products grouped by kernel configuration; INT8 products
-    // with their planes in one stream-ordered workspace
+    // with their planes in one stream-ordered workspace.  Requests that run
+    // beside others fill the chip together and each runs whole; a request
+    // launched alone on an idle device takes the planner's split-K (a narrow
+    // product's few output tiles spread over the CUs by k-range), its
+    // residues per k-range after its planes in the workspace.
     std::map<std::tuple<int, int, int, int>, std::vector<Fp64Args>> f64;
     std::map<int, std::vector<Int8Args>> i8;
+    const bool solo = idle && batch.size() == 1;
     size_t ws = 0;
-    std::vector<size_t> offs;
+    std::vector<size_t> offs, part_off;
+    std::vector<int> splits;
     for (uint64_t t : batch) {
       Request& r = reqs[t];
+      const mmp_job& j = r.job;
       offs.push_back(ws);
-      if (r.plan.form == MMP_FORM_INT8_WORDS && r.job.m > 0 && r.job.n > 0 && r.job.k > 0)
-        ws += (r.plan.workspace_bytes + 255) / 256 * 256;
+      part_off.push_back(0);
+      splits.push_back(1);
+      if (j.m == 0 || j.n == 0 || j.k == 0) continue;
+      size_t need = 0;
+      if (r.plan.form == MMP_FORM_INT8_WORDS)
+        need = int8_planes_bytes(r.plan.digits_a, j.m, j.n, j.k, r.res_a != nullptr, r.res_b != nullptr);
+      if (solo && r.solo_splits > 1) {
+        splits.back() = r.solo_splits;
+        part_off.back() = need;
+        need += 8 * (size_t)r.solo_splits * (size_t)j.m * (size_t)j.n;
+      }
+      ws += (need + 255) / 256 * 256;
     }
     void* work = nullptr;
     bool owned = false;
@@ -183,14 +202,19 @@ struct mmp_server {
         err = launch_zero_fill(j.C, j.m, j.n, j.ldc, s);
         continue;
       }
+      double* partial = splits[i] > 1 ? (double*)((char*)work + offs[i] + part_off[i]) : nullptr;
       if (r.plan.form == MMP_FORM_FP64_WORDS) {
-        f64[std::make_tuple(r.plan.u, r.plan.v, r.plan.tile, fp64_class(r.plan.slots, r.plan.kblock))].push_back(
-            make_fp64_args(r.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc));
+        Fp64Args a = make_fp64_args(r.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc);
+        a.splits = splits[i];
+        a.partial = partial;
+        f64[std::make_tuple(r.plan.u, r.plan.v, r.plan.tile, fp64_class(r.plan.slots, r.plan.kblock))].push_back(a);
       } else {
         Int8Args g = make_int8_args(r.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc,
                                     (int8_t*)work + offs[i]);
         g.resident_a = r.res_a ? r.res_a->planes : nullptr;
         g.resident_b = r.res_b ? r.res_b->planes : nullptr;
+        g.splits = splits[i];
+        g.partial = partial;
         err = launch_int8_digitize(r.plan.digits_a, g, s);
         i8[r.plan.digits_a].push_back(g);
       }
@@ -207,6 +231,12 @@ struct mmp_server {
     for (auto& kv : i8)
       for (size_t c = 0; c < kv.second.size() && !err; c += kMaxBatch)
         err = launch_int8_gemm(kv.first, kv.second.data() + c, (int)std::min<size_t>(kMaxBatch, kv.second.size() - c), s);
+    for (size_t i = 0; i < batch.size() && !err; i++) {
+      if (splits[i] < 2) continue;
+      const mmp_job& j = reqs[batch[i]].job;
+      err = launch_splitk_reduce((const double*)((char*)work + offs[i] + part_off[i]), splits[i], j.m, j.n,
+                                 (double)j.p, j.C, j.ldc, s);
+    }
     const int st2 = release_workspace(work, owned, s);
     if (err) return err;
     return st2;
@@ -428,6 +458,7 @@ int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
       r.res_a = s->find_resident(j.A, j.m, j.k, j.lda, j.p, 0, r.plan.digits_a, kp);
       r.res_b = s->find_resident(j.B, j.k, j.n, j.ldb, j.p, 1, r.plan.digits_b, kp);
     }
+    r.solo_splits = default_splits(r.plan, j.m, j.n, j.k);
     r.footprint = s->request_footprint(r);
     if (r.footprint > s->budget - s->resident) {
       s->stats.rejected += 1;

@@ -214,12 +214,15 @@ int launch_splitk_reduce(const double* partial, int splits, int64_t m, int64_t n
 }
 
 int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split) {
-  // enough workgroups for 256 CUs (two per CU), each split a sizeable
-  // k-range; a power of two, so that from 8 on every XCD of the round-robin
-  // dispatch owns whole k-ranges (the kernels put the k-range in the low
-  // bits of the workgroup id)
-  if (tiles >= 512 || stages < 2 * min_stages_per_split) return 1;
-  const int64_t want = (512 + tiles - 1) / tiles;
+  // Output tiles that cannot fill 256 CUs twice get k-ranges: enough for four
+  // rounds of 512 workgroups, so that the last, partly filled round costs
+  // little (with one or two rounds a 171-tile product spent a third of its
+  // time in a round a third full), each split a sizeable k-range; a power
+  // of two, so that from 8 on every XCD of the round-robin dispatch owns
+  // whole k-ranges (the kernels put the k-range in the low bits of the
+  // workgroup id)
+  if (tiles <= 0 || tiles >= 512 || stages < 2 * min_stages_per_split) return 1;
+  const int64_t want = (4 * 512 + tiles - 1) / tiles;
   const int64_t cap = std::min<int64_t>(stages / min_stages_per_split, 64);
   int64_t s = 1;
   while (s < want && 2 * s <= cap) s *= 2;

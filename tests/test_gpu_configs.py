@@ -139,6 +139,12 @@ def test_unbalanced_10923x32768x32(bits):
         srv.register_operand(dA, prob.p, 0)
         assert srv.wait(srv.submit(dA, dB, C, prob.p), 120.0)[0] == 0
     outs.append(C)
+    # A's digit planes prepared once, reused by direct calls
+    pa = mmp.prepare_operand(dA, prob.p, 0)
+    for _ in range(2):
+        C = torch.full((prob.m, prob.n), -1.0, dtype=torch.float64, device="cuda")
+        mmp.mm_modp_async(dA, dB, C, prob.p, prepared_a=pa)
+        outs.append(C)
     torch.cuda.synchronize()
-    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    assert all(torch.equal(outs[0], c) for c in outs[1:])
     _check_sampled(prob, A, B, outs[0], nrows=2, ncols=1, nrand=256)

@@ -166,3 +166,41 @@ def test_split_k_int8(splits):
     A = gen.random_matrix(1, 1, 40, 3000, p)
     B = gen.random_matrix(1, 2, 3000, 30, p)
     assert_exact(run(p, A, B, splits=splits, force_kblock=128), oracle.mm_modp(p, A, B))
+
+
+@pytest.mark.parametrize("p", [251, 65521, 8388593, 2147483647, 68719476731, 1125899906842597, 4503599627370449])
+def test_prepared_operands(p):
+    # digit planes made once (A, B or both) give the product of the plain call
+    for (m, n, k) in ((17, 33, 29), (130, 70, 300), (33, 40, 1000)):
+        A = gen.random_matrix(m + n, 1, m, k, p)
+        B = gen.random_matrix(m + n, 2, k, n, p)
+        want = oracle.mm_modp(p, A, B)
+        dA, dB = dev(A), dev(B)
+        pa = mmp.prepare_operand(dA, p, 0)
+        pb = mmp.prepare_operand(dB, p, 1)
+        assert pa.planes.numel() == pa.desc.digits * m * (-(-k // 64) * 64)
+        for kw in ({"prepared_a": pa}, {"prepared_b": pb}, {"prepared_a": pa, "prepared_b": pb},
+                   {"prepared_a": pa, "splits": 3}, {"prepared_b": pb, "force_kblock": 64}):
+            say("prepared", p, m, n, k, sorted(kw))
+            C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+            mmp.mm_modp_async(dA, dB, C, p, **kw)
+            torch.cuda.synchronize()
+            assert_exact(C.cpu().numpy(), want)
+
+
+def test_prepared_operand_strided_and_reused():
+    # planes of a strided view; reused across several B, with a caller workspace
+    p = 1099511627689
+    m, n, k = 90, 50, 700
+    Abig = gen.random_matrix(5, 1, m, k + 13, p)
+    dAbig = dev(Abig)
+    dA = dAbig[:, :k]
+    pa = mmp.prepare_operand(dA, p, 0)
+    ws = torch.empty(mmp.plan(p, m, n, k, form=INT8)["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    for t in range(3):
+        B = gen.random_matrix(5, 10 + t, k, n, p)
+        C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+        say("prepared reuse", t)
+        mmp.mm_modp_async(dA, dev(B), C, p, prepared_a=pa, workspace=ws)
+        torch.cuda.synchronize()
+        assert_exact(C.cpu().numpy(), oracle.mm_modp(p, Abig[:, :k], B))

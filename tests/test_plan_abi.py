@@ -201,6 +201,53 @@ def test_argument_errors_before_device_work():
     assert lib.mm_modp(33554393, 1, 1, 4, 0, 4, None, None, None) == 0
 
 
+def test_prepared_operand_host_checks():
+    lib = mmp.lib()
+    p = 68719476731  # 36 bits: 5 digits
+    # digits x outer x (inner rounded up to 64)
+    assert lib.mmp_operand_bytes(p, 0, 10, 100) == 5 * 10 * 128
+    assert lib.mmp_operand_bytes(p, 1, 100, 10) == 5 * 10 * 128
+    assert lib.mmp_operand_bytes(p, 0, 3, 64) == 5 * 3 * 64
+    for bad in ((p, 2, 10, 10), (p, 0, 0, 10), (p, 1, 10, -1), (3, 0, 10, 10)):
+        assert lib.mmp_operand_bytes(*bad) == 0
+    fake, buf = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000)
+    d = mmp.MmpOperand()
+    need = 5 * 10 * 128
+    # buffer too small, missing out, bad side, ld < cols: refused before any launch
+    assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 100, buf, need - 1, ctypes.byref(d), None) == -1
+    assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 100, buf, need, None, None) == -1
+    assert lib.mmp_prepare_operand(p, 2, fake, 10, 100, 100, buf, need, ctypes.byref(d), None) == -1
+    assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 99, buf, need, ctypes.byref(d), None) == -1
+    # the planner and the other entry points refuse prepared operands
+    d.planes, d.p, d.side, d.digits, d.rows, d.cols, d.kp = 0x100000, p, 0, 5, 8, 8, 64
+    o = mmp.MmpOpts()
+    o.prepared_a = ctypes.pointer(d)
+    out = mmp.MmpPlan()
+    assert lib.mmp_plan(p, 0, 0, 8, 8, 8, ctypes.byref(o), ctypes.byref(out)) == -1
+    job = mmp.MmpJob(p, 0, 0, 8, 8, 8, 0x1000, 8, 0x9000, 8, 0x20000, 8)
+    assert lib.mm_modp_batched(ctypes.byref(job), 1, ctypes.byref(o), None) == -1
+    A, B, C = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x9000), ctypes.c_void_p(0x20000)
+
+    def call(opts, m=8, n=8, k=8, pp=p, u=0):
+        return lib.mm_modp_async(ctypes.byref(opts), pp, u, u, m, n, k, A, k, B, n, C, n, None)
+    # planes that do not describe the operand: other modulus, shape, side or digits
+    assert call(o, pp=1099511627689) == -1
+    assert call(o, m=9) == -1
+    assert call(o, k=70) == -1
+    for field, val in (("side", 1), ("digits", 4), ("kp", 128), ("planes", None)):
+        saved = getattr(d, field)
+        setattr(d, field, val)
+        assert call(o) == -1, field
+        setattr(d, field, saved)
+    # forced FP64 words or word counts with prepared planes
+    o.form = mmp.FORM_FP64_WORDS
+    assert call(o) == -1
+    o.form = 0
+    assert call(o, u=1) == -1
+    o.centered_words = 1
+    assert call(o) == -1
+
+
 # ------------------------------------------------------------------ schedule emulation
 # The kernel accumulates L word products per block, reduces (correction-free
 # when the plan says lazy), and finishes with a complete reduction and the
@@ -582,9 +629,9 @@ def test_int8_fold_exact(p):
 @pytest.mark.parametrize("form", [1, 2])
 def test_split_policy(shape, form):
     # k-ranges only when the output tiles cannot fill 256 CUs twice, a power of
-    # two (whole k-ranges per XCD from 8 on), each range at least 1024 (FP64)
-    # or 2048 (INT8) k-terms; the FP64 tile is the largest that reaches 512
-    # workgroups with them
+    # two (whole k-ranges per XCD from 8 on), the smallest that gives four
+    # rounds of 512 workgroups unless a range would drop below 1024 (FP64)
+    # or 2048 (INT8) k-terms
     m, n, k = shape
     p = 8388593
     pl = mmp.plan(p, m, n, k, form=form)
@@ -596,5 +643,6 @@ def test_split_policy(shape, form):
     if tiles >= 512:
         assert s_ == 1
     if s_ > 1:
-        assert k // s_ >= per and tiles * s_ // 2 < 512
+        assert k // s_ >= per and tiles * s_ // 2 < 4 * 512
+        assert tiles * s_ >= 4 * 512 or k // (2 * s_) < per or s_ == 64
         assert pl["workspace_bytes"] >= 8 * s_ * m * n
