@@ -16,6 +16,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -266,6 +267,48 @@ def bench_crt(args, mmp, torch, gen):
     mnk = float(job.m) * job.n * job.k
     d = (job.bits + 1 + 7) // 8
     gemm_ms = phases.get("crt_gemm", (1, 0.0))[1]
+    # Chinese remainder reconstruction of the integer product: from all the
+    # moduli, and from the shortest prefix whose product exceeds
+    # k (2^bits - 1)^2 (eq. CRT2); the two must agree on every entry
+    bound = job.k * ((1 << job.bits) - 1) ** 2
+    M, s_min = 1, 0
+    for i, p in enumerate(job.primes):
+        M *= p
+        if M > bound:
+            s_min = i + 1
+            break
+    rec = {}
+    outs_rec = {}
+    for name, use in (("all_moduli", len(job.primes)), ("eq_crt2_moduli", s_min)):
+        r_in, mods = outs[:use], job.primes[:use]
+        limbs = mmp.crt_limbs(mods)
+        o = torch.empty((limbs, job.m, job.n), dtype=torch.int64, device="cuda")
+        t = _time(torch, lambda: mmp.crt_reconstruct(r_in, mods, out=o), 2, args.steps)
+        rec[name] = {"moduli": use, "limbs": limbs, "ms": round(t, 4),
+                     "entries_per_s": round(job.m * job.n / (t * 1e-3), 1)}
+        outs_rec[name] = o
+    lf = outs_rec["eq_crt2_moduli"].shape[0]
+    same = bool(torch.equal(outs_rec["all_moduli"][:lf], outs_rec["eq_crt2_moduli"])) and \
+        bool(torch.all(outs_rec["all_moduli"][lf:] == 0))
+    if not same:
+        log("RECONSTRUCTIONS DIFFER")
+        sys.exit(1)
+    rec["identical_low_limbs"] = same
+    # product counts: eq. numprodMM (multimodular moduli) against the
+    # multiword count (eq. numprodMW's least uv) and the planner's FP64 words
+    counts = []
+    for b in sorted({p.bit_length() for p in job.primes}):
+        p = next(x for x in job.primes if x.bit_length() == b)
+        row = {"bits": b}
+        for lam in (1, 512):
+            row[f"multimodular_lambda{lam}"] = math.ceil((4 * math.log2(p) + 2 * math.log2(job.k)) /
+                                                        (53 - math.log2(lam)))
+            row[f"multiword_lambda{lam}"] = min(
+                (u * v for u, v in ((1, 1), (1, 2), (1, 3), (1, 4), (2, 2), (2, 3))
+                 if u * v >= (u + v) * math.log2(p) / (53 - math.log2(lam))), default=None)
+        pl = mmp.plan(p, job.m, job.n, job.k, form=1)
+        row["planner_fp64_uv"] = pl["u"] * pl["v"]
+        counts.append(row)
     print(json.dumps({
         "metric": "effective 2mnk GFLOP/s over all moduli of the CRT job",
         "value": round(len(job.primes) * 2 * mnk / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s",
@@ -275,7 +318,8 @@ def bench_crt(args, mmp, torch, gen):
         "roofline": {"bound": "mfma", "kernel": "crt_gemm_kernel", "kernel_ms": round(gemm_ms, 4),
                      "achieved": round(2 * d * d * mnk / (gemm_ms * 1e-3) / 1e12, 2) if gemm_ms else None,
                      "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s"},
-        "phases_ms": {k: round(v[1], 4) for k, v in phases.items()}}), flush=True)
+        "phases_ms": {k: round(v[1], 4) for k, v in phases.items()},
+        "reconstruction": rec, "product_counts": counts}), flush=True)
 
 
 def sweep_bits(args, mmp, torch, gen):

@@ -256,6 +256,26 @@ int mm_modp_crt(const mmp_opts *opts, const uint64_t *A, int64_t lda,
 size_t mmp_workspace_crt(int64_t m, int64_t n, int64_t k, int entry_bits,
                          int nprimes, const mmp_opts *opts);
 
+/* Chinese remainder reconstruction (Section 5.2): for every entry (i, j) of
+ * nmoduli residue matrices, the unique integer X in [0, M), M = moduli[0]
+ * ... moduli[nmoduli - 1], with X = C[t][i][j] mod moduli[t] for every t.
+ * X is the integer product A B that mm_modp_crt's residues come from when M
+ * exceeds its entries (eq. CRT2: M > k (2^entry_bits - 1)^2).
+ *   C: HOST array of nmoduli DEVICE pointers to m x n binary64 residues
+ *      (integers in [0, moduli[t]), leading dimension ldc);
+ *   moduli: HOST array, 1 <= nmoduli <= 64, pairwise coprime, each in
+ *      [2, 2^52 / 3] (the range where Alg. 2 is exact for factors below the
+ *      modulus, Prop. Joris);
+ *   out: DEVICE, X as `limbs` little-endian 64-bit words in planes: word w of
+ *      entry (i, j) at out[(w m + i) ldo + j]; limbs must hold M - 1.
+ * Computed on the device: Garner's mixed-radix digits in binary64 modular
+ * arithmetic (Alg. 1, Alg. 2), then Horner into the limbs.  Asynchronous on
+ * `stream`; MMP_EINVAL for bad arguments, before any launch. */
+int mmp_crt_reconstruct(const double *const *C, int64_t ldc,
+                        const uint64_t *moduli, int nmoduli, int64_t m,
+                        int64_t n, uint64_t *out, int64_t ldo, int limbs,
+                        void *stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request server on one device: products of mixed shapes and moduli are

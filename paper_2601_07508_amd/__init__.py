@@ -242,6 +242,41 @@ def mm_modp_async(A, B, C, p: int, u: int = 0, v: int = 0, stream=None, **opts):
     return C
 
 
+def crt_limbs(moduli) -> int:
+    """64-bit limbs that hold every integer below the product of ``moduli``."""
+    M = 1
+    for m in moduli:
+        M *= int(m)
+    return max(1, ((M - 1).bit_length() + 63) // 64)
+
+
+def crt_reconstruct(residues, moduli, limbs: int = 0, out=None, stream=None):
+    """The integers X in [0, prod(moduli)) with X = residues[t] mod moduli[t]
+    entry by entry (see mmp_crt_reconstruct).  ``residues``: equally shaped
+    float64 CUDA matrices.  Returns a (limbs, m, n) int64 CUDA tensor holding
+    the 64-bit limbs, least significant first (reinterpret as unsigned)."""
+    import torch
+    if len(residues) != len(moduli) or not residues:
+        raise ValueError("one residue matrix per modulus")
+    for c in residues:
+        _check_mat(c, "residue")
+    m, n = residues[0].shape
+    ldc = max(residues[0].stride(0), 1)
+    if any(tuple(c.shape) != (m, n) or max(c.stride(0), 1) != ldc for c in residues):
+        raise ValueError("residue matrices must share shape and leading dimension")
+    limbs = limbs or crt_limbs(moduli)
+    if out is None:
+        out = torch.empty((limbs, m, n), dtype=torch.int64, device=residues[0].device)
+    if out.dim() != 3 or tuple(out.shape[:2]) != (limbs, m) or out.shape[2] < n or out.stride(2) != 1 \
+            or out.stride(0) != m * out.stride(1):
+        raise ValueError("out must be (limbs, m, >= n) with planes of m rows")
+    ptrs = (_vp * len(residues))(*[c.data_ptr() for c in residues])
+    mods = (_u64 * len(moduli))(*[int(x) for x in moduli])
+    _check(_lib.mmp_crt_reconstruct(ptrs, ldc, mods, len(moduli), m, n, out.data_ptr(), max(out.stride(1), 1),
+                                    limbs, _stream_ptr(stream)), "mmp_crt_reconstruct")
+    return out
+
+
 class PreparedOperand:
     """The INT8 digit planes of one operand (see mmp_prepare_operand); pass it
     as ``prepared_a=`` / ``prepared_b=`` to mm_modp_async.  Holds the planes'
@@ -374,6 +409,9 @@ _lib.mmp_server_destroy.argtypes = [_vp]
 _lib.mmp_server_destroy.restype = _int
 _lib.mmp_register_operand.argtypes = [_vp, _vp, _i64, _i64, _i64, _u64, _int, ctypes.POINTER(_u64)]
 _lib.mmp_register_operand.restype = _int
+_lib.mmp_crt_reconstruct.argtypes = [ctypes.POINTER(_vp), _i64, ctypes.POINTER(_u64), _int, _i64, _i64, _vp, _i64,
+                                     _int, _vp]
+_lib.mmp_crt_reconstruct.restype = _int
 _lib.mmp_operand_bytes.argtypes = [_u64, _int, _i64, _i64]
 _lib.mmp_operand_bytes.restype = _sz
 _lib.mmp_prepare_operand.argtypes = [_u64, _int, _vp, _i64, _i64, _i64, _vp, _sz, ctypes.POINTER(MmpOperand), _vp]

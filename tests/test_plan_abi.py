@@ -248,6 +248,32 @@ def test_prepared_operand_host_checks():
     assert call(o) == -1
 
 
+def test_crt_reconstruct_host_checks():
+    lib = mmp.lib()
+    vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+    ptrs = (vp * 3)(0x100000, 0x200000, 0x300000)
+    out = vp(0x10000000)
+
+    def call(moduli, m=4, n=4, ldc=4, ldo=4, limbs=4, C=ptrs, o=out):
+        mods = (u64 * len(moduli))(*moduli)
+        return lib.mmp_crt_reconstruct(C, ldc, mods, len(moduli), m, n, o, ldo, limbs, None)
+    good = [1000003, 1000033, 1000037]
+    assert call(good, m=0) == 0 and call(good, n=0) == 0          # empty: nothing launched
+    assert call([6, 9, 5]) == -1                                   # not coprime
+    assert call([1000003, 1 << 51, 7]) == -1                       # above 2^52 / 3
+    assert call([1, 5, 7]) == -1                                   # below 2
+    assert call(good, limbs=0) == -1                               # M needs one limb
+    big = [(1 << 50) - 35, (1 << 50) - 27, (1 << 50) - 11]         # M near 2^150: three limbs
+    assert call(big, limbs=2) == -1
+    assert call(good, ldc=3) == -1 and call(good, ldo=3) == -1
+    assert call(good, o=None) == -1
+    assert call(good, C=(vp * 3)(0x100000, None, 0x300000)) == -1
+    assert call(good, o=vp(0x100000 + 8)) == -1                    # out overlaps a residue matrix
+    mods = (u64 * 65)(*([3] * 65))
+    assert lib.mmp_crt_reconstruct(ptrs, 4, mods, 65, 4, 4, out, 4, 4, None) == -1
+    assert lib.mmp_crt_reconstruct(ptrs, 4, mods, 0, 4, 4, out, 4, 4, None) == -1
+
+
 # ------------------------------------------------------------------ schedule emulation
 # The kernel accumulates L word products per block, reduces (correction-free
 # when the plan says lazy), and finishes with a complete reduction and the
