@@ -37,7 +37,7 @@ def log(*a):
 # counter record taken on other sources than these is stale.
 KERNEL_SOURCES = {
     1: ["fp64_words_kernel.h", "mmp_fp64_words.hip"],
-    2: ["int8_digits_kernel.h", "mmp_int8_digits.hip"],
+    2: ["int8_digits_kernel.h"],  # the digit GEMM (the digitize passes live in int8_digitize_kernel.h)
 }
 
 

@@ -1,0 +1,140 @@
+// Digit planes of the INT8-digit form: entries of A and B written as D
+// signed base-256 digits, one int8 plane per digit (the digit GEMM in
+// int8_digits_kernel.h reads them).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mmp {
+namespace i8d {
+
+// Signed base-256 digits of an integer v with -128 R <= v <= 127 R,
+// R = (256^D - 1) / 255: the low byte read as int8 is the digit, and the
+// exact quotient (v - d) / 256 carries on.
+template <int D>
+__device__ __forceinline__ void digits_of_int(int64_t v, int8_t (&d)[D]) {
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int8_t di = (int8_t)(v & 0xff);
+    d[i] = di;
+    v = (v - di) >> 8;
+  }
+}
+
+// Entry loaders.  Residues: x in [0, p) stored as binary64; the digits are
+// those of x' = x, or x - p when x exceeds 127 R (then x' >= -128 R because
+// p <= 256^D).  Integers: uint64 entries below 2^62, taken as they are.
+struct ResidueIn {
+  const double* X;
+  int64_t p, top;
+  // x < 2^52 is an integer: x + 2^52 is exact and its significand is x
+  __device__ __forceinline__ int64_t conv(double x) const {
+    const int64_t v = __double_as_longlong(x + 4503599627370496.0) - 0x4330000000000000ll;
+    return v > top ? v - p : v;
+  }
+  __device__ __forceinline__ int64_t operator()(int64_t idx) const { return conv(X[idx]); }
+  // 8 entries from a 16-byte aligned address
+  __device__ __forceinline__ void load8(int64_t idx, int64_t (&v)[8]) const {
+    const double2* q = (const double2*)(X + idx);
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      const double2 w = q[h];
+      v[2 * h] = conv(w.x);
+      v[2 * h + 1] = conv(w.y);
+    }
+  }
+};
+struct IntegerIn {
+  const uint64_t* X;
+  __device__ __forceinline__ int64_t operator()(int64_t idx) const { return (int64_t)X[idx]; }
+  __device__ __forceinline__ void load8(int64_t idx, int64_t (&v)[8]) const {
+    const ulonglong2* q = (const ulonglong2*)(X + idx);
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      const ulonglong2 w = q[h];
+      v[2 * h] = (int64_t)w.x;
+      v[2 * h + 1] = (int64_t)w.y;
+    }
+  }
+};
+
+// A (rows x cols, row-major, ld) -> planes out[D][rows][kp], k zero-padded to kp.
+// Grid: x over 2048-column chunks of a row, y over rows (strided).  Each
+// thread digitises 8 consecutive columns and stores one 8-byte word per plane
+// (a wave writes 512 contiguous bytes per plane).  VEC: the row's entries are
+// 16-byte aligned (aligned base, even ld), so whole groups of 8 load as four
+// 16-byte vectors.
+template <int D, class In, bool VEC>
+__global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, int64_t cols, int64_t ld,
+                                                            int64_t kp, int8_t* __restrict__ out) {
+  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+  if (c0 >= kp) return;
+  const int64_t plane = rows * kp;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    int64_t v[8];
+    if (VEC && c0 + 8 <= cols) {
+      X.load8(r * ld + c0, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; e++) v[e] = (c0 + e < cols) ? X(r * ld + c0 + e) : 0;
+    }
+    uint64_t packed[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) packed[i] = 0;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      int8_t d[D];
+      digits_of_int<D>(v[e], d);
+#pragma unroll
+      for (int i = 0; i < D; i++) packed[i] |= (uint64_t)(uint8_t)d[i] << (8 * e);
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) *(uint64_t*)(out + i * plane + r * kp + c0) = packed[i];
+  }
+}
+
+// B (krows x ncols, row-major, ld) -> transposed planes out[D][ncols][kp].
+// 64 x 64 tiles through LDS so that both the reads (along n) and the writes
+// (along k) are contiguous.
+template <int D, class In>
+__global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows, int64_t ncols, int64_t ld,
+                                                            int64_t kp, int8_t* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint8_t tile[D][64][64 + 4];
+  const int64_t tiles_n = (ncols + 63) / 64;
+  const int64_t k0 = (int64_t)(blockIdx.x / tiles_n) * 64;
+  const int64_t n0 = (int64_t)(blockIdx.x % tiles_n) * 64;
+  const int tid = threadIdx.x;
+  // read: 64 k-rows x 64 columns; thread tid takes column tid % 64 of k-rows
+  // tid / 64 + 4 u, u < 16, all 16 loads issued before any is used
+  const int nn = tid % 64, kb = tid / 64;
+  const int64_t col = n0 + nn;
+  int64_t v[16];
+#pragma unroll
+  for (int u = 0; u < 16; u++) {
+    const int64_t row = k0 + kb + 4 * u;
+    v[u] = (row < krows && col < ncols) ? X(row * ld + col) : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < 16; u++) {
+    int8_t d[D];
+    digits_of_int<D>(v[u], d);
+#pragma unroll
+    for (int i = 0; i < D; i++) tile[i][nn][kb + 4 * u] = (uint8_t)d[i];
+  }
+  __syncthreads();
+  // write: for each plane and column, 64 k-bytes as 16 words
+  const int64_t plane = ncols * kp;
+#pragma unroll
+  for (int e = tid; e < D * 64 * 16; e += 256) {
+    const int i = e / (64 * 16);
+    const int rem = e % (64 * 16);
+    const int cn = rem / 16, w = rem % 16;
+    const int64_t ocol = n0 + cn, kq = k0 + 4 * w;
+    if (ocol < ncols && kq < kp)  // 4 digit bytes, k-order, read as one word (rows are 68 bytes)
+      *(uint32_t*)(out + i * plane + ocol * kp + kq) = *(const uint32_t*)&tile[i][cn][4 * w];
+  }
+}
+
+}  // namespace i8d
+}  // namespace mmp

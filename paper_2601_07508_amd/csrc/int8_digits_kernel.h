@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "int8_digitize_kernel.h"
 #include "mmp_internal.h"
 
 namespace mmp {
@@ -61,109 +62,6 @@ __device__ __forceinline__ double fold_weights(const int (&w)[ND], double p, dou
 __device__ __forceinline__ double addmod(double x, double y, double p) {
   const double s = x + y;
   return (s >= p) ? s - p : s;
-}
-
-// Signed base-256 digits of an integer v with -128 R <= v <= 127 R,
-// R = (256^D - 1) / 255: the low byte read as int8 is the digit, and the
-// exact quotient (v - d) / 256 carries on.
-template <int D>
-__device__ __forceinline__ void digits_of_int(int64_t v, int8_t (&d)[D]) {
-#pragma unroll
-  for (int i = 0; i < D; i++) {
-    const int8_t di = (int8_t)(v & 0xff);
-    d[i] = di;
-    v = (v - di) >> 8;
-  }
-}
-
-// Entry loaders.  Residues: x in [0, p) stored as binary64; the digits are
-// those of x' = x, or x - p when x exceeds 127 R (then x' >= -128 R because
-// p <= 256^D).  Integers: uint64 entries below 2^62, taken as they are.
-struct ResidueIn {
-  const double* X;
-  int64_t p, top;
-  __device__ __forceinline__ int64_t operator()(int64_t idx) const {
-    int64_t v = (int64_t)X[idx];
-    return v > top ? v - p : v;
-  }
-};
-struct IntegerIn {
-  const uint64_t* X;
-  __device__ __forceinline__ int64_t operator()(int64_t idx) const { return (int64_t)X[idx]; }
-};
-
-// A (rows x cols, row-major, ld) -> planes out[D][rows][kp], k zero-padded to kp.
-template <int D, class In>
-__global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, int64_t cols, int64_t ld,
-                                                            int64_t kp, int8_t* __restrict__ out) {
-  // each thread: 4 consecutive columns of one row -> one 32-bit store per plane
-  const int64_t quads = kp / 4;
-  const int64_t total = rows * quads;
-  const int64_t plane = rows * kp;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = t / quads;
-    const int64_t c0 = (t - r * quads) * 4;
-    uint32_t packed[D];
-#pragma unroll
-    for (int i = 0; i < D; i++) packed[i] = 0;
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      const int64_t c = c0 + e;
-      int8_t d[D];
-      if (c < cols) {
-        digits_of_int<D>(X(r * ld + c), d);
-      } else {
-#pragma unroll
-        for (int i = 0; i < D; i++) d[i] = 0;
-      }
-#pragma unroll
-      for (int i = 0; i < D; i++) packed[i] |= (uint32_t)(uint8_t)d[i] << (8 * e);
-    }
-#pragma unroll
-    for (int i = 0; i < D; i++) *(uint32_t*)(out + i * plane + r * kp + c0) = packed[i];
-  }
-}
-
-// B (krows x ncols, row-major, ld) -> transposed planes out[D][ncols][kp].
-// 64 x 64 tiles through LDS so that both the reads (along n) and the writes
-// (along k) are contiguous.
-template <int D, class In>
-__global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows, int64_t ncols, int64_t ld,
-                                                            int64_t kp, int8_t* __restrict__ out) {
-  __shared__ uint8_t tile[D][64][64 + 4];
-  const int64_t tiles_n = (ncols + 63) / 64;
-  const int64_t k0 = (int64_t)(blockIdx.x / tiles_n) * 64;
-  const int64_t n0 = (int64_t)(blockIdx.x % tiles_n) * 64;
-  const int tid = threadIdx.x;
-  // read: 64 k-rows x 64 columns, 16 elements per thread
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int kk = e / 64, nn = e % 64;
-    const int64_t row = k0 + kk, col = n0 + nn;
-    int8_t d[D];
-    if (row < krows && col < ncols) {
-      digits_of_int<D>(X(row * ld + col), d);
-    } else {
-#pragma unroll
-      for (int i = 0; i < D; i++) d[i] = 0;
-    }
-#pragma unroll
-    for (int i = 0; i < D; i++) tile[i][nn][kk] = (uint8_t)d[i];
-  }
-  __syncthreads();
-  // write: for each plane and column, 64 k-bytes as 16 words
-  const int64_t plane = ncols * kp;
-  for (int e = tid; e < D * 64 * 16; e += 256) {
-    const int i = e / (64 * 16);
-    const int rem = e % (64 * 16);
-    const int nn = rem / 16, w = rem % 16;
-    const int64_t col = n0 + nn, kq = k0 + 4 * w;
-    if (col < ncols && kq < kp) {
-      const uint32_t v = (uint32_t)tile[i][nn][4 * w] | ((uint32_t)tile[i][nn][4 * w + 1] << 8) |
-                         ((uint32_t)tile[i][nn][4 * w + 2] << 16) | ((uint32_t)tile[i][nn][4 * w + 3] << 24);
-      *(uint32_t*)(out + i * plane + col * kp + kq) = v;
-    }
-  }
 }
 
 struct GemmArgs {

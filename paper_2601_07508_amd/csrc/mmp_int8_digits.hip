@@ -11,6 +11,24 @@
 
 namespace mmp {
 
+namespace {
+// Row digitizing launch: x over 2048-column chunks, y over rows (strided
+// beyond 65535); the vector form when every row starts 16-byte aligned.
+template <int D, class In, class T>
+hipError_t launch_digitize_rows(const In& in, const T* X, int64_t rows, int64_t cols, int64_t ld, int64_t kp,
+                                int8_t* out, hipStream_t s, TimerTok* t) {
+  if (rows <= 0 || kp <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((kp + 2047) / 2048), (unsigned)std::min<int64_t>(rows, 65535));
+  if (((uintptr_t)X % 16) == 0 && ld % 2 == 0)
+    hipExtLaunchKernelGGL((i8d::digitize_rows_kernel<D, In, true>), grid, dim3(256), 0, s, timer_start(t),
+                          timer_stop(t), 0, in, rows, cols, ld, kp, out);
+  else
+    hipExtLaunchKernelGGL((i8d::digitize_rows_kernel<D, In, false>), grid, dim3(256), 0, s, timer_start(t),
+                          timer_stop(t), 0, in, rows, cols, ld, kp, out);
+  return hipGetLastError();
+}
+}  // namespace
+
 #if MMP_D <= 7  // residues of p < 2^52 need at most 7 digits
 
 // side 0: X is A (rows x cols = m x k) -> planes [D][m][kp];
@@ -25,12 +43,8 @@ int MMP_CAT(launch_int8_digitize_side_, MMP_D)(int side, const double* X, int64_
   for (int i = 0; i < D; i++) top = top * 256 + 127;
   const ResidueIn in{X, (int64_t)p, top};
   if (side == 0) {
-    const int64_t total = rows * (kp / 4);
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
     TimerTok* t = timer_begin("int8_digitize_a");
-    hipExtLaunchKernelGGL((digitize_rows_kernel<D, ResidueIn>), dim3((unsigned)blocks), dim3(256), 0, s,
-                          timer_start(t), timer_stop(t), 0, in, rows, cols, ld, kp, out);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = launch_digitize_rows<D>(in, X, rows, cols, ld, kp, out, s, t);
     timer_commit(t, (int)e);
     return (int)e;
   }
@@ -108,12 +122,8 @@ int MMP_CAT(launch_crt_, MMP_D)(const CrtLaunch& c, void* stream) {
   int8_t* Bd = c.work + (size_t)D * c.m * kp;
   {
     const IntegerIn in{c.A};
-    const int64_t total = c.m * (kp / 4);
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
     TimerTok* t = timer_begin("crt_digitize_a");
-    hipExtLaunchKernelGGL((digitize_rows_kernel<D, IntegerIn>), dim3((unsigned)blocks), dim3(256), 0, s,
-                          timer_start(t), timer_stop(t), 0, in, c.m, c.k, c.lda, kp, Ad);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = launch_digitize_rows<D>(in, c.A, c.m, c.k, c.lda, kp, Ad, s, t);
     timer_commit(t, (int)e);
     if (e) return (int)e;
   }
