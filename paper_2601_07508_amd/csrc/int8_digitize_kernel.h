@@ -126,7 +126,8 @@ __global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows,
   // write: for each plane and column, 64 k-bytes as 16 words
   const int64_t plane = ncols * kp;
 #pragma unroll
-  for (int e = tid; e < D * 64 * 16; e += 256) {
+  for (int u = 0; u < 4 * D; u++) {  // D x 64 columns x 16 words over 256 threads
+    const int e = tid + 256 * u;
     const int i = e / (64 * 16);
     const int rem = e % (64 * 16);
     const int cn = rem / 16, w = rem % 16;

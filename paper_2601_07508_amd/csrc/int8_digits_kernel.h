@@ -98,29 +98,35 @@ struct GemmBatch {
 // = (2D - 1) TM TN 4.  Two waves per SIMD hide the LDS and load latency, so
 // every shape keeps a wave within 256 VGPRs: 4-wave groups (two groups per
 // CU) up to 5 digits, one 8-wave group with narrower wave tiles beyond.
-template <int D>
+// NARROW (products with n <= 32): 64 x 32 tiles, so that no digit product
+// is spent on padding columns; 16 x 32 wave tiles in 4-wave groups up to 5
+// digits, 16 x 16 in an 8-wave group beyond.
+template <int D, bool NARROW = false>
 struct I8Shape {
-  static constexpr int WM = 2;
-  static constexpr int WN = D <= 5 ? 2 : 4;
-  static constexpr int TM = 2;
-  static constexpr int TN = D <= 5 ? 2 : 1;
+  static constexpr int WM = NARROW ? 4 : 2;
+  static constexpr int WN = NARROW ? (D <= 5 ? 1 : 2) : (D <= 5 ? 2 : 4);
+  static constexpr int TM = NARROW ? 1 : 2;
+  static constexpr int TN = NARROW ? (D <= 5 ? 2 : 1) : (D <= 5 ? 2 : 1);
   static constexpr int BM = WM * TM * 16;  // 64
-  static constexpr int BN = WN * TN * 16;  // 64
+  static constexpr int BN = WN * TN * 16;  // 64, or 32 when NARROW
   static constexpr int THREADS = 64 * WM * WN;
   static constexpr int GROUPS_PER_CU = D <= 5 ? 2 : 1;
+  // LDS stages in the ring: three for the narrow tiles wherever the groups
+  // per CU still fit (these products stream A's planes from HBM, and a
+  // 64 x 32 stage computes in less time than one copy's latency), else two
+  static constexpr int STAGES = (NARROW && D != 5) ? 3 : 2;
 };
 
-// Ring of two LDS stages; each holds D digit planes of a BM x 64 slab of A
+// Ring of NS LDS stages; each holds D digit planes of a BM x 64 slab of A
 // and of a BN x 64 slab of B^T, 64 bytes per row with no padding.  The four
 // 16-byte chunks of row r are stored in the order q ^ f(r) with
 // f(r) = ((r >> 2) ^ (r >> 1)) & 3.  An operand read takes chunk q of 16
 // consecutive rows; f keeps those chunks in distinct banks whether the LDS
 // serves 16 lanes over 256 bytes (distinct (r & 3, q ^ f)) or 8 lanes over
 // 128 bytes (distinct (r & 1, q ^ f) within each 8 rows).
-constexpr int kStages = 2;
-template <int D, int BM, int BN>
+template <int D, int BM, int BN, int NS>
 struct DigitRing {
-  int8_t s[kStages][D][BM + BN][64];
+  int8_t s[NS][D][BM + BN][64];
 };
 
 __device__ __forceinline__ int swz(int r, int q) { return ((q ^ (r >> 2) ^ (r >> 1)) & 3) * 16; }
@@ -144,13 +150,13 @@ template <int D, class S, class Fold>
 __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, const int8_t* __restrict__ Bd,
                                                 int64_t m, int64_t n, int64_t kp, int64_t m0, int64_t n0,
                                                 int64_t st_begin, int64_t st_end,
-                                                int64_t stages_per_block, DigitRing<D, S::BM, S::BN>& sm,
+                                                int64_t stages_per_block,
+                                                DigitRing<D, S::BM, S::BN, S::STAGES>& sm,
                                                 int4v (&acc)[2 * D - 1][S::TM][S::TN], Fold fold) {
   constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
   constexpr int NW = S::WM * S::WN;
   constexpr int GROUPS = D * (BM + BN) / 16;  // 1 KB copy instructions per stage
-  static_assert(GROUPS % NW == 0, "whole copy instructions per wave");
-  constexpr int IPW = GROUPS / NW;
+  constexpr int IPW = (GROUPS + NW - 1) / NW;   // per wave; the last ones may idle
   static_assert(IPW < 64, "vmcnt range");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
@@ -170,7 +176,9 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
 #pragma unroll
   for (int e = 0; e < IPW; e++) {
     const int t = wv + NW * e;
-    if (t < D * BM / 16) {
+    if (t >= GROUPS) {
+      voff[e] = 0;  // no copy
+    } else if (t < D * BM / 16) {
       const int64_t row = m0 + 16 * (t % (BM / 16)) + rl;
       voff[e] = (uint64_t)((row < m ? row : m - 1) * kp + 16 * ql);
     } else {
@@ -178,43 +186,56 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
       voff[e] = (uint64_t)((row < n ? row : n - 1) * kp + 16 * ql);
     }
   }
-  auto issue = [&](int64_t st) {
-    const int b = (int)(st & 1);
+  // copies this wave issues per stage
+  const int mine = (GROUPS % NW == 0 || wv < GROUPS % NW) ? IPW : IPW - 1;
+  auto issue = [&](int64_t st, int b) {
 #pragma unroll
     for (int e = 0; e < IPW; e++) {
       const int t = wv + NW * e;
-      const int8_t* base;
-      int plane, row0;
+      if (GROUPS % NW != 0 && t >= GROUPS) continue;  // uniform per wave
       if (t < D * BM / 16) {
-        plane = t / (BM / 16);
-        row0 = 16 * (t % (BM / 16));
-        base = Ad + plane * planeA + st * 64;
+        const int plane = t / (BM / 16), row0 = 16 * (t % (BM / 16));
+        const int8_t* base = Ad + plane * planeA + st * 64;
+        __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
+                                         (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
       } else {
         const int t2 = t - D * BM / 16;
-        plane = t2 / (BN / 16);
-        row0 = BM + 16 * (t2 % (BN / 16));
-        base = Bd + plane * planeB + st * 64;
+        const int plane = t2 / (BN / 16), row0 = BM + 16 * (t2 % (BN / 16));
+        const int8_t* base = Bd + plane * planeB + st * 64;
+        __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
+                                         (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
       }
-      __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
-                                       (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
     }
   };
 
+  constexpr int NS = S::STAGES;
   const int lrow = lane & 15, lq = lane >> 4;
-  if (st_begin < st_end) issue(st_begin);
+  // the first NS - 1 stages in flight before the loop
+#pragma unroll
+  for (int i = 0; i < NS - 1; i++)
+    if (st_begin + i < st_end) issue(st_begin + i, i);
   int64_t in_block = 0;
+  int b = 0;  // buffer of stage st: (st - st_begin) mod NS
   for (int64_t st = st_begin; st < st_end; st++) {
-    // This wave's copies of stage st are complete; the barrier extends that
-    // to every wave and ends the reads of stage st - 1, whose buffer the
-    // next copies overwrite.  A bare barrier: a fence here would also wait
-    // for copies that may still be in flight; the empty asm statements keep
-    // the compiler from moving LDS accesses or copies across it.
-    wait_vm<0>();
+    // This wave's copies of stage st are complete (with three stages, the
+    // next stage's copies, issued after them, may still be in flight); the
+    // barrier extends that to every wave and ends the reads of stage st - 1,
+    // whose buffer the next copies overwrite.  A bare barrier: a fence here
+    // would also wait for copies that may still be in flight; the empty asm
+    // statements keep the compiler from moving LDS accesses or copies
+    // across it.
+    if (NS == 3 && st + 1 < st_end) {
+      if (mine == IPW)
+        wait_vm<IPW>();
+      else
+        wait_vm<(IPW > 0 ? IPW - 1 : 0)>();
+    } else {
+      wait_vm<0>();
+    }
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (st + 1 < st_end) issue(st + 1);
-    const int b = (int)(st & 1);
+    if (st + NS - 1 < st_end) issue(st + NS - 1, b == 0 ? NS - 1 : b - 1);
     int4v bf[D][TN];
 #pragma unroll
     for (int j = 0; j < D; j++)
@@ -243,17 +264,18 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
       in_block = 0;
       fold();
     }
+    b = (b + 1 == NS) ? 0 : b + 1;
   }
   if (in_block != 0) fold();
 }
 
-template <int D>
-__global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) void int8_digits_gemm_kernel(
-    const GemmBatch bt) {
-  using S = I8Shape<D>;
+template <int D, bool NARROW>
+__global__ __launch_bounds__((I8Shape<D, NARROW>::THREADS), (I8Shape<D, NARROW>::GROUPS_PER_CU)) void
+int8_digits_gemm_kernel(const GemmBatch bt) {
+  using S = I8Shape<D, NARROW>;
   constexpr int ND = 2 * D - 1;
   constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
-  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN> sm;
+  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN, S::STAGES> sm;
 
   int job = 0;
   while (job + 1 < bt.njobs && (int)blockIdx.x >= bt.tile_start[job + 1]) job++;
@@ -354,7 +376,7 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
   using S = I8Shape<D>;
   constexpr int ND = 2 * D - 1;
   constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
-  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN> sm;
+  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN, S::STAGES> sm;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);

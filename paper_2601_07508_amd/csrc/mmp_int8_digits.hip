@@ -70,11 +70,13 @@ int MMP_CAT(launch_int8_digitize_, MMP_D)(const Int8Args& g, void* stream) {
   return 0;
 }
 
-int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* stream) {
+namespace {
+template <bool NARROW>
+int launch_gemm(const Int8Args* jobs, int njobs, hipStream_t s) {
   using namespace i8d;
   constexpr int D = MMP_D;
-  constexpr int BM = I8Shape<D>::BM, BN = I8Shape<D>::BN;
-  if (njobs < 1 || njobs > kMaxBatch) return (int)hipErrorInvalidValue;
+  using S = I8Shape<D, NARROW>;
+  constexpr int BM = S::BM, BN = S::BN;
   GemmBatch b;
   b.njobs = njobs;
   int64_t total = 0;
@@ -99,13 +101,22 @@ int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* str
   }
   b.tile_start[njobs] = (int)total;
   if (total <= 0) return 0;
-  hipStream_t s = (hipStream_t)stream;
   TimerTok* t = timer_begin("int8_gemm");
-  hipExtLaunchKernelGGL((int8_digits_gemm_kernel<D>), dim3((unsigned)total), dim3(I8Shape<D>::THREADS), 0, s,
+  hipExtLaunchKernelGGL((int8_digits_gemm_kernel<D, NARROW>), dim3((unsigned)total), dim3(S::THREADS), 0, s,
                         timer_start(t), timer_stop(t), 0, b);
   const int e = (int)hipGetLastError();
   timer_commit(t, e);
   return e;
+}
+}  // namespace
+
+// 64 x 32 tiles when every product of the launch has n <= 32, else 64 x 64.
+int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* stream) {
+  if (njobs < 1 || njobs > kMaxBatch) return (int)hipErrorInvalidValue;
+  bool narrow = true;
+  for (int j = 0; j < njobs; j++) narrow = narrow && jobs[j].n <= 32;
+  return narrow ? launch_gemm<true>(jobs, njobs, (hipStream_t)stream)
+                : launch_gemm<false>(jobs, njobs, (hipStream_t)stream);
 }
 
 #endif

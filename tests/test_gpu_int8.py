@@ -204,3 +204,43 @@ def test_prepared_operand_strided_and_reused():
         mmp.mm_modp_async(dA, dev(B), C, p, prepared_a=pa, workspace=ws)
         torch.cuda.synchronize()
         assert_exact(C.cpu().numpy(), oracle.mm_modp(p, Abig[:, :k], B))
+
+
+@pytest.mark.parametrize("p", [251, 65521, 8388593, 2147483647, 68719476731, 281474976710597, 4503599627370449])
+def test_int8_narrow_columns(p):
+    # n <= 32 runs 64 x 32 tiles: every digit count, ragged m and k, n at and
+    # below the tile width, split-K and short int32 blocks
+    for (m, n, k) in ((1, 1, 1), (70, 32, 200), (129, 31, 77), (64, 16, 1000), (200, 1, 130)):
+        A = gen.random_matrix(m * n, 1, m, k, p)
+        B = gen.random_matrix(m * n, 2, k, n, p)
+        want = oracle.mm_modp(p, A, B)
+        say("int8 narrow", p, m, n, k)
+        assert_exact(run(p, A, B), want)
+        assert_exact(run(p, A, B, splits=3), want)
+        if k >= 128:
+            assert_exact(run(p, A, B, force_kblock=64), want)
+    # all digits at their extremes
+    m, n, k = 65, 32, 300
+    Aall = np.full((m, k), p - 1, dtype=np.uint64)
+    Ball = np.full((k, n), p - 1, dtype=np.uint64)
+    assert_exact(run(p, Aall, Ball), oracle.mm_modp(p, Aall, Ball))
+
+
+def test_int8_batch_mixed_widths():
+    # one launch per digit count: narrow tiles only when every product has n <= 32
+    p = 1099511627689
+    shapes = [(50, 32, 100), (40, 20, 300), (30, 33, 90)]
+    for sel in ([0, 1], [0, 1, 2]):
+        jobs, want = [], []
+        for i in sel:
+            m, n, k = shapes[i]
+            A = gen.random_matrix(i, 1, m, k, p)
+            B = gen.random_matrix(i, 2, k, n, p)
+            C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+            jobs.append((dev(A), dev(B), C, p, 0, 0))
+            want.append(oracle.mm_modp(p, A, B))
+        say("int8 batch widths", sel)
+        mmp.mm_modp_batched(jobs, form=INT8)
+        torch.cuda.synchronize()
+        for (_, _, C, *_), w in zip(jobs, want):
+            assert_exact(C.cpu().numpy(), w)
