@@ -211,7 +211,8 @@ size_t mmp_operand_bytes(uint64_t p, int side, int64_t rows, int64_t cols);
  * digits are those the INT8 form makes per call (the multiword split of
  * Section 3.1 with 8-bit words, the low-precision words of Section 6).
  * Asynchronous; `planes` must stay valid and unchanged while products use
- * it.  MMP_EINVAL for bad arguments or a buffer too small. */
+ * it.  MMP_EINVAL for bad arguments, a buffer too small or one that
+ * overlaps M. */
 int mmp_prepare_operand(uint64_t p, int side, const double *M, int64_t rows,
                         int64_t cols, int64_t ld, void *planes,
                         size_t planes_bytes, mmp_operand_t *out,

@@ -355,6 +355,7 @@ int mmp_prepare_operand(uint64_t p, int side, const double* M, int64_t rows, int
   try {
     const size_t need = mmp_operand_bytes(p, side, rows, cols);
     if (!out || !M || !planes || need == 0 || ld < cols || planes_bytes < need) return MMP_EINVAL;
+    if (ranges_overlap(planes, need, M, span_bytes(rows, cols, ld))) return MMP_EINVAL;
     const int64_t inner = side == 0 ? cols : rows;
     mmp_operand_t o;
     std::memset(&o, 0, sizeof(o));

@@ -221,3 +221,56 @@ def test_autotune_picks_a_correct_plan():
         torch.cuda.synchronize()
         assert np.array_equal(C.cpu().numpy(), oracle.mm_modp(p, A, B).astype(np.float64))
     mmp.tune_cache_clear()
+
+
+def test_graph_capture_reconstruction_and_prepared_product_replays():
+    # CRT residues + their reconstruction + a product with prepared A planes,
+    # captured once and replayed with eager work in between
+    bits = 60
+    m, n, k = 70, 40, 256
+    primes = gen.crt_primes(count=6)
+    A = gen.uniform_bits(6, 1, m * k, bits).reshape(m, k)
+    B = gen.uniform_bits(6, 2, k * n, bits).reshape(k, n)
+    dA, dB = dev64(A), dev64(B)
+    outs = [torch.zeros((m, n), dtype=torch.float64, device="cuda") for _ in primes]
+    ws = torch.empty(mmp.workspace_crt(m, n, k, bits, len(primes)), dtype=torch.uint8, device="cuda")
+    limbs = mmp.crt_limbs(primes)
+    rec = torch.zeros((limbs, m, n), dtype=torch.int64, device="cuda")
+    p = 1099511627689
+    A2 = gen.random_matrix(8, 1, 90, 3000, p)
+    B2 = gen.random_matrix(8, 2, 3000, 20, p)
+    dA2, dB2 = dev(A2), dev(B2)
+    C2 = torch.zeros((90, 20), dtype=torch.float64, device="cuda")
+    pl = mmp.plan(p, 90, 20, 3000, form=mmp.FORM_INT8_WORDS)
+    pws = torch.empty(pl["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pa = mmp.prepare_operand(dA2, p, 0, stream=s)
+
+        def work():
+            mmp.mm_modp_crt(dA, dB, primes, outs, bits, stream=s, workspace=ws)
+            mmp.crt_reconstruct(outs, primes, out=rec, stream=s)
+            mmp.mm_modp_async(dA2, dB2, C2, p, stream=s, prepared_a=pa, workspace=pws)
+        work()  # warm-up outside the graph
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        work()
+    exact = [[sum(int(A[i, l]) * int(B[l, j]) for l in range(k)) for j in range(n)] for i in range(m)]
+    want2 = oracle.mm_modp(p, A2, B2).astype(np.float64)
+    for rep in range(3):
+        rec.fill_(-1)
+        C2.fill_(-1.0)
+        for C in outs:
+            C.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        L = rec.cpu().numpy().view(np.uint64)
+        got = [[sum(int(L[w, i, j]) << (64 * w) for w in range(limbs)) for j in range(n)] for i in range(m)]
+        assert got == exact, rep
+        assert np.array_equal(C2.cpu().numpy(), want2), rep
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        del x

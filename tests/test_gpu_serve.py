@@ -144,3 +144,35 @@ def test_resident_operand_switches_auto_to_int8_form():
     assert "fp64_words" not in t or t["fp64_words"][0] == 0
     want = oracle.mm_modp(p, A, B).astype(np.float64)
     assert np.array_equal(C.cpu().numpy(), want)
+
+
+def test_lone_request_takes_split_k():
+    # a request launched alone on an idle server runs the planner's split-K
+    # (here FP64 words with forced (1,2): 4 output tiles, long k); requests
+    # launched beside others run whole; every result equals the oracle's
+    p = 67108859
+    m = n = 100
+    k = 40000
+    A = gen.random_matrix(7, 1, m, k, p)
+    B = gen.random_matrix(7, 2, k, n, p)
+    want = oracle.mm_modp(p, A, B).astype(np.float64)
+    dA, dB = dev(A), dev(B)
+    assert mmp.plan(p, m, n, k, 1, 2)["splits"] > 1
+    C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+    with mmp.Server(hbm_budget=4 << 30, max_slots=8) as srv:
+        mmp.timers_read(reset=True)
+        mmp.timers_enable(True)
+        assert srv.wait(srv.submit(dA, dB, C, p, 1, 2), 60.0)[0] == 0
+        torch.cuda.synchronize()
+        mmp.timers_enable(False)
+        t = mmp.timers_read(reset=True)
+        say("lone request timers", t)
+        assert t.get("fp64_words", (0, 0))[0] == 1 and t.get("splitk_reduce", (0, 0))[0] == 1
+        assert np.array_equal(C.cpu().numpy(), want)
+        # several at once: correct whether or not each ran alone
+        Cs = [torch.full((m, n), -1.0, dtype=torch.float64, device="cuda") for _ in range(4)]
+        tickets = [srv.submit(dA, dB, c, p, 1, 2) for c in Cs]
+        for tk in tickets:
+            assert srv.wait(tk, 60.0)[0] == 0
+    for c in Cs:
+        assert np.array_equal(c.cpu().numpy(), want)

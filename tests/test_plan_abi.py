@@ -218,6 +218,9 @@ def test_prepared_operand_host_checks():
     assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 100, buf, need, None, None) == -1
     assert lib.mmp_prepare_operand(p, 2, fake, 10, 100, 100, buf, need, ctypes.byref(d), None) == -1
     assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 99, buf, need, ctypes.byref(d), None) == -1
+    # planes overlapping the matrix they are made from
+    assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 100, ctypes.c_void_p(0x1000 + 800), need,
+                                   ctypes.byref(d), None) == -1
     # the planner and the other entry points refuse prepared operands
     d.planes, d.p, d.side, d.digits, d.rows, d.cols, d.kp = 0x100000, p, 0, 5, 8, 8, 64
     o = mmp.MmpOpts()
