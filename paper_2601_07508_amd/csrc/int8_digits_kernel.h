@@ -176,7 +176,7 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
 #pragma unroll
   for (int e = 0; e < IPW; e++) {
     const int t = wv + NW * e;
-    if (t >= GROUPS) {
+    if (GROUPS % NW != 0 && t >= GROUPS) {
       voff[e] = 0;  // no copy
     } else if (t < D * BM / 16) {
       const int64_t row = m0 + 16 * (t % (BM / 16)) + rl;
@@ -193,18 +193,20 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
     for (int e = 0; e < IPW; e++) {
       const int t = wv + NW * e;
       if (GROUPS % NW != 0 && t >= GROUPS) continue;  // uniform per wave
+      const int8_t* base;
+      int plane, row0;
       if (t < D * BM / 16) {
-        const int plane = t / (BM / 16), row0 = 16 * (t % (BM / 16));
-        const int8_t* base = Ad + plane * planeA + st * 64;
-        __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
-                                         (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
+        plane = t / (BM / 16);
+        row0 = 16 * (t % (BM / 16));
+        base = Ad + plane * planeA + st * 64;
       } else {
         const int t2 = t - D * BM / 16;
-        const int plane = t2 / (BN / 16), row0 = BM + 16 * (t2 % (BN / 16));
-        const int8_t* base = Bd + plane * planeB + st * 64;
-        __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
-                                         (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
+        plane = t2 / (BN / 16);
+        row0 = BM + 16 * (t2 % (BN / 16));
+        base = Bd + plane * planeB + st * 64;
       }
+      __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
+                                       (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
     }
   };
 
@@ -213,10 +215,12 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
   // the first NS - 1 stages in flight before the loop
 #pragma unroll
   for (int i = 0; i < NS - 1; i++)
-    if (st_begin + i < st_end) issue(st_begin + i, i);
+    if (st_begin + i < st_end) issue(st_begin + i, NS == 2 ? (int)((st_begin + i) & 1) : i);
   int64_t in_block = 0;
-  int b = 0;  // buffer of stage st: (st - st_begin) mod NS
+  int b3 = 0;  // three stages: buffer of stage st, (st - st_begin) mod 3
   for (int64_t st = st_begin; st < st_end; st++) {
+    // two stages: buffer st & 1 (the prologue filled buffer st_begin & 1)
+    const int b = NS == 2 ? (int)(st & 1) : b3;
     // This wave's copies of stage st are complete (with three stages, the
     // next stage's copies, issued after them, may still be in flight); the
     // barrier extends that to every wave and ends the reads of stage st - 1,
@@ -235,7 +239,7 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (st + NS - 1 < st_end) issue(st + NS - 1, b == 0 ? NS - 1 : b - 1);
+    if (st + NS - 1 < st_end) issue(st + NS - 1, NS == 2 ? (int)((st + 1) & 1) : (b == 0 ? NS - 1 : b - 1));
     int4v bf[D][TN];
 #pragma unroll
     for (int j = 0; j < D; j++)
@@ -264,7 +268,7 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
       in_block = 0;
       fold();
     }
-    b = (b + 1 == NS) ? 0 : b + 1;
+    if (NS == 3) b3 = (b3 + 1 == NS) ? 0 : b3 + 1;
   }
   if (in_block != 0) fold();
 }
