@@ -444,7 +444,8 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     else if (L % 4 == 0) S = (int)L;
     else return MMP_EINVAL;  // longer blocks must be whole MFMA k-steps
     if (L > ((int64_t)1 << 26)) return MMP_EINVAL;
-    bk = {L, S, centered || ext || (!strict && lazy_block_ok(p, bu, bv, L)), ext, block_cost(S, L, false)};
+    const bool lazy = centered || ext || (!strict && lazy_block_ok(p, bu, bv, L));
+    bk = {L, S, lazy, ext, block_cost(S, L, lazy)};
   } else if (u != 0) {
     bk = choose_kblock(p, bu, bv, k, strict, extended, centered);
   }

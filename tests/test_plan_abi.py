@@ -160,6 +160,16 @@ def test_forced_kblock():
         mmp.plan(p, 64, 64, 64, 2, 2, force_kblock=102)  # > 16 and not whole k-steps
 
 
+def test_forced_block_estimate_matches_the_planner_s_own():
+    # forcing the block the planner would choose changes nothing, estimate included
+    for p, shape in ((1125899906842597, (8192, 8192, 8192)), (68719476731, (4096, 4096, 4096)),
+                     (33554393, (512, 512, 512))):
+        auto = mmp.plan(p, *shape, form=1)
+        forced = mmp.plan(p, *shape, auto["u"], auto["v"], form=1, force_kblock=auto["kblock"])
+        for key in ("kblock", "slots", "lazy", "tile", "est_seconds"):
+            assert forced[key] == pytest.approx(auto[key]), (p, key)
+
+
 def test_reserved_options_rejected():
     o = mmp.MmpOpts()
     o.reserved[0] = 1
