@@ -267,6 +267,8 @@ def crt_reconstruct(residues, moduli, limbs: int = 0, out=None, stream=None):
     limbs = limbs or crt_limbs(moduli)
     if out is None:
         out = torch.empty((limbs, m, n), dtype=torch.int64, device=residues[0].device)
+    if not isinstance(out, torch.Tensor) or out.dtype not in (torch.int64, torch.uint64) or not out.is_cuda:
+        raise TypeError("out must be an int64/uint64 CUDA tensor")
     if out.dim() != 3 or tuple(out.shape[:2]) != (limbs, m) or out.shape[2] < n or out.stride(2) != 1 \
             or out.stride(0) != m * out.stride(1):
         raise ValueError("out must be (limbs, m, >= n) with planes of m rows")
