@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "mmp_internal.h"
 
@@ -88,25 +89,26 @@ __device__ __forceinline__ double addmod(double x, double y, double p) {
 }
 
 // Alg. 4 on one entry, with the library's centered variant.
-//   paper words (rbias = 0): x = sum_i a^i w[i] with 0 <= w[i] < a; each
+//   paper words (CEN = false): x = sum_i a^i w[i] with 0 <= w[i] < a; each
 //     quotient is floor(t / a): r = floor(fl(t ainv)) with ainv = fl(1/a) is
 //     exact when a is a power of two and otherwise within one of the
 //     quotient (t < 2^53), so one correction step in each direction makes it
 //     exact (fix = 1);
-//   centered words (cen = 1, rbias = 1/2): x is first taken to x - p when
+//   centered words (CEN = true): x is first taken to x - p when
 //     2x > p, and r = floor(fl(t ainv + 1/2)) rounds to nearest within
 //     |t| 2^-52 < 1/2, so |w[i]| < a/2 + 1 below the top word with no
 //     correction; x - (0 or p) = sum_i a^i w[i] exactly either way.
-// Branch-free: cen and fix are uniform over the launch.
-template <int W>
-__device__ __forceinline__ void split_entry(double x, double p, double a, double ainv, double rbias, bool cen,
-                                            bool fix, double (&w)[W]) {
-  double t = (cen && x + x > p) ? x - p : x;
+// Branch-free: fix is uniform over the launch; CEN is a template argument
+// (the caller branches once per stage), so paper words pay nothing for it.
+template <int W, bool CEN>
+__device__ __forceinline__ void split_entry(double x, double p, double a, double ainv, bool fix, double (&w)[W]) {
+  constexpr double rbias = CEN ? 0.5 : 0.0;
+  double t = (CEN && x + x > p) ? x - p : x;
 #pragma unroll
   for (int i = 0; i < W - 1; i++) {
     double r = floor(fma(t, ainv, rbias));
     double d = fma(-a, r, t);
-    if (fix) {
+    if (!CEN && fix) {
       const bool lo = d < 0.0;
       r = lo ? r - 1.0 : r;
       d = lo ? d + a : d;
@@ -244,7 +246,6 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
   }
   const double p = a.p, q = a.q, bias = a.bias;
   const bool cen = a.centered != 0;
-  const double rbias = cen ? 0.5 : 0.0;
   const bool afix = !cen && a.afix, bfix = !cen && a.bfix;
 
   double ra[NA], rb[NB];
@@ -274,11 +275,12 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
       for (int e = 0; e < NB; e++) rb[e] = (b_meta[e] >> 16) < lim ? rb[e] : 0.0;
     }
   };
-  auto store_stage = [&](int buf) {
+  auto store_stage_as = [&](int buf, auto centered) {
+    constexpr bool CEN = decltype(centered)::value;
 #pragma unroll
     for (int e = 0; e < NA; e++) {
       double w[U];
-      split_entry<U>(ra[e], p, a.alpha, a.ainv, rbias, cen, afix, w);
+      split_entry<U, CEN>(ra[e], p, a.alpha, a.ainv, afix, w);
       const int dst = PAD ? (a_meta[PAD ? e : 0] & 0xffff) : a_dst0 + e * AROWS * LDA;
 #pragma unroll
       for (int i = 0; i < U; i++) (&As[buf][i][0][0])[dst] = w[i];
@@ -286,11 +288,18 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
 #pragma unroll
     for (int e = 0; e < NB; e++) {
       double w[V];
-      split_entry<V>(rb[e], p, a.beta, a.binv, rbias, cen, bfix, w);
+      split_entry<V, CEN>(rb[e], p, a.beta, a.binv, bfix, w);
       const int dst = PAD ? (b_meta[PAD ? e : 0] & 0xffff) : b_dst0 + e * BROWS * LDB;
 #pragma unroll
       for (int j = 0; j < V; j++) (&Bs[buf][j][0][0])[dst] = w[j];
     }
+  };
+  // one uniform branch per stage between the paper's words and centered words
+  auto store_stage = [&](int buf) {
+    if (cen)
+      store_stage_as(buf, std::true_type{});
+    else
+      store_stage_as(buf, std::false_type{});
   };
 
   d4 acc[U][V][TM][TN];
