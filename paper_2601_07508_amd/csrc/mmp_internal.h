@@ -129,6 +129,7 @@ int launch_splitk_reduce(const double* partial, int splits, int64_t m, int64_t n
                          void* stream);
 // Split count for a product of `tiles` output tiles and `stages` k-stages.
 int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split);
+int choose_splits_fill(int64_t tiles, int64_t stages, int64_t min_stages_per_split);  // INT8 digit GEMM
 // the planner's split-K for a plan (its form, tile and block) and shape
 int default_splits(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k);
 // Digit planes of one operand side into out (side 0: A rows -> [D][rows][kp];

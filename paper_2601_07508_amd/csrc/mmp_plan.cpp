@@ -305,7 +305,7 @@ int digits_for(uint64_t p) {
 }
 
 int default_splits(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k) {
-  if (pl.form == MMP_FORM_INT8_WORDS) return choose_splits(cdiv(m, 64) * cdiv(n, 64), cdiv(k, 64), 32);
+  if (pl.form == MMP_FORM_INT8_WORDS) return choose_splits_fill(cdiv(m, 64) * cdiv(n, 64), cdiv(k, 64), 32);
   // real k-terms per 16-slot stage: fewer only when blocks leave zero slots
   const int64_t KR = (pl.slots <= kBK && pl.kblock < pl.slots) ? (kBK / pl.slots) * pl.kblock : kBK;
   return choose_splits(cdiv(m, pl.bm) * cdiv(n, pl.bn), cdiv(k, KR), 64);

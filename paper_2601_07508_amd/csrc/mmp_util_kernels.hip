@@ -214,7 +214,7 @@ int launch_splitk_reduce(const double* partial, int splits, int64_t m, int64_t n
 }
 
 int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split) {
-  // Output tiles that cannot fill 256 CUs twice get k-ranges: enough for four
+  // The FP64-word kernel.  Output tiles that cannot fill 256 CUs twice get k-ranges: enough for four
   // rounds of 512 workgroups, so that the last, partly filled round costs
   // little (with one or two rounds a 171-tile product spent a third of its
   // time in a round a third full), each split a sizeable k-range; a power
@@ -226,6 +226,24 @@ int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split) {
   const int64_t cap = std::min<int64_t>(stages / min_stages_per_split, 64);
   int64_t s = 1;
   while (s < want && 2 * s <= cap) s *= 2;
+  return (int)s;
+}
+
+int choose_splits_fill(int64_t tiles, int64_t stages, int64_t min_stages_per_split) {
+  // The digit GEMM: the fewest k-ranges (a power of two) that fill one round
+  // of 512 workgroups, doubled while the last round is less than 90% full.
+  // More k-ranges than that cost time here: each XCD then holds several
+  // k-ranges' digit slabs at once in its L2 (512 x 512 x 131072 at 23 bits:
+  // 0.395 ms at 8 k-ranges, 0.496 ms at 32).
+  if (tiles <= 0 || tiles >= 512 || stages < 2 * min_stages_per_split) return 1;
+  const int64_t cap = std::min<int64_t>(stages / min_stages_per_split, 64);
+  int64_t s = 1;
+  while (tiles * s < 512 && 2 * s <= cap) s *= 2;
+  auto fill = [&](int64_t x) {
+    const int64_t w = tiles * x, rounds = (w + 511) / 512;
+    return (double)w / (double)(512 * rounds);
+  };
+  while (fill(s) < 0.9 && 2 * s <= cap) s *= 2;
   return (int)s;
 }
 

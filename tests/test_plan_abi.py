@@ -664,13 +664,14 @@ def test_int8_fold_exact(p):
 
 
 @pytest.mark.parametrize("shape", [(512, 512, 131072), (16384, 16384, 256), (4096, 4096, 4096), (64, 64, 1 << 20),
-                                   (1000, 30, 50000)])
+                                   (1000, 30, 50000), (10923, 32, 32768), (1024, 1024, 65536), (256, 2048, 65536)])
 @pytest.mark.parametrize("form", [1, 2])
 def test_split_policy(shape, form):
     # k-ranges only when the output tiles cannot fill 256 CUs twice, a power of
-    # two (whole k-ranges per XCD from 8 on), the smallest that gives four
-    # rounds of 512 workgroups unless a range would drop below 1024 (FP64)
-    # or 2048 (INT8) k-terms
+    # two (whole k-ranges per XCD from 8 on), each range at least 1024 (FP64)
+    # or 2048 (INT8) k-terms.  FP64 words: the smallest count that gives four
+    # rounds of 512 workgroups.  INT8 digits: the smallest that fills one
+    # round, doubled while the last round is less than 90% full.
     m, n, k = shape
     p = 8388593
     pl = mmp.plan(p, m, n, k, form=form)
@@ -679,9 +680,19 @@ def test_split_policy(shape, form):
     bm, bn = (pl["bm"], pl["bn"]) if form == 1 else (64, 64)
     tiles = -(-m // bm) * -(-n // bn)
     per = 1024 if form == 1 else 2048
+    cap = min(k // per, 64)
     if tiles >= 512:
         assert s_ == 1
     if s_ > 1:
-        assert k // s_ >= per and tiles * s_ // 2 < 4 * 512
-        assert tiles * s_ >= 4 * 512 or k // (2 * s_) < per or s_ == 64
+        assert k // s_ >= per
         assert pl["workspace_bytes"] >= 8 * s_ * m * n
+    if tiles < 512 and k >= 2 * per:
+        if form == 1:
+            assert tiles * s_ >= 4 * 512 or 2 * s_ > cap
+            assert s_ == 1 or tiles * s_ // 2 < 4 * 512
+        else:
+            def fill(x):
+                w = tiles * x
+                return w / (512 * -(-w // 512))
+            assert (tiles * s_ >= 512 and fill(s_) >= 0.9) or 2 * s_ > cap
+            assert s_ == 1 or tiles * s_ // 2 < 512 or fill(s_ // 2) < 0.9
