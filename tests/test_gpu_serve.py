@@ -176,3 +176,24 @@ def test_lone_request_takes_split_k():
             assert srv.wait(tk, 60.0)[0] == 0
     for c in Cs:
         assert np.array_equal(c.cpu().numpy(), want)
+
+
+def test_resident_b_operand():
+    # a registered B (side 1): requests with different A reuse its digit planes
+    p = 68719476731
+    k, n = 700, 90
+    B = gen.random_matrix(21, 2, k, n, p)
+    dB = dev(B)
+    with mmp.Server(hbm_budget=4 << 30, max_slots=8) as srv:
+        h = srv.register_operand(dB, p, 1)
+        assert srv.stats()["resident_bytes"] == 5 * n * 704
+        outs = []
+        for i, m in enumerate((1, 33, 200)):
+            A = gen.random_matrix(40 + i, 1, m, k, p)
+            C = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+            outs.append((srv.submit(dev(A), dB, C, p), A, C))
+        for t, A, C in outs:
+            assert srv.wait(t, 60.0)[0] == 0
+            assert np.array_equal(C.cpu().numpy(), oracle.mm_modp(p, A, B).astype(np.float64))
+        srv.unregister_operand(h)
+        assert srv.stats()["resident_bytes"] == 0
