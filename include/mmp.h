@@ -72,8 +72,10 @@ enum {
  * benchmark of Section 4.1, whose decomposition the paper times apart from
  * the products.  Filled by the library; the caller owns the planes' memory. */
 typedef struct {
-  const int8_t *planes;   /* device; [digits][outer][kp] signed base-256
-                             digits (outer = rows of an A, cols of a B) */
+  const int8_t *planes;   /* device; `digits` planes of outer x kp signed
+                             base-256 digits (outer = rows of an A, cols of
+                             a B), each in 1 KB blocks of 16 outer rows by
+                             64 inner bytes; the layout is the library's */
   uint64_t p;             /* the modulus the entries were reduced for */
   int side;               /* 0: an A (rows x cols = m x k); 1: a B (k x n) */
   int digits;             /* ceil(bits(p) / 8) */
@@ -200,8 +202,8 @@ int mm_modp_async(const mmp_opts *opts, uint64_t p, int u, int v, int64_t m,
                   void *stream);
 
 /* Device bytes of one operand's digit planes (0 for invalid arguments):
- * digits x outer x kp, with outer = rows of an A (side 0) or cols of a B
- * (side 1) and kp the inner dimension rounded up to 64. */
+ * digits x outer16 x kp, with outer16 the rows of an A (side 0) or cols of a
+ * B (side 1) rounded up to 16 and kp the inner dimension rounded up to 64. */
 size_t mmp_operand_bytes(uint64_t p, int side, int64_t rows, int64_t cols);
 
 /* Writes the signed base-256 digit planes of M (entries in [0, p), row

@@ -1,6 +1,9 @@
 // Digit planes of the INT8-digit form: entries of A and B written as D
 // signed base-256 digits, one int8 plane per digit (the digit GEMM in
-// int8_digits_kernel.h reads them).
+// int8_digits_kernel.h reads them).  A plane of R rows by kp k-bytes is
+// stored in 1 KB blocks of 16 rows by 64 k-bytes (plane_at), R rounded up to
+// 16: the GEMM's copies then read 1 KB contiguous runs, and a row group's
+// successive k-stages follow one another in memory.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -8,6 +11,13 @@
 
 namespace mmp {
 namespace i8d {
+
+// byte offset of (row r, k-byte c) within a plane of kp k-bytes per row
+__device__ __forceinline__ int64_t plane_at(int64_t r, int64_t c, int64_t kp) {
+  return (r >> 4) * (kp << 4) + (c >> 6) * 1024 + (r & 15) * 64 + (c & 63);
+}
+// bytes of one plane of `rows` rows
+__device__ __forceinline__ int64_t plane_size(int64_t rows, int64_t kp) { return ((rows + 15) & ~(int64_t)15) * kp; }
 
 // Signed base-256 digits of an integer v with -128 R <= v <= 127 R,
 // R = (256^D - 1) / 255: the low byte read as int8 is the digit, and the
@@ -59,10 +69,10 @@ struct IntegerIn {
   }
 };
 
-// A (rows x cols, row-major, ld) -> planes out[D][rows][kp], k zero-padded to kp.
+// A (rows x cols, row-major, ld) -> D planes of rows x kp, k zero-padded to kp.
 // Grid: x over 2048-column chunks of a row, y over rows (strided).  Each
 // thread digitises 8 consecutive columns and stores one 8-byte word per plane
-// (a wave writes 512 contiguous bytes per plane).  VEC: the row's entries are
+// (a wave fills eight whole 64-byte block rows per plane).  VEC: the row's entries are
 // 16-byte aligned (aligned base, even ld), so whole groups of 8 load as four
 // 16-byte vectors.
 template <int D, class In, bool VEC>
@@ -70,7 +80,7 @@ __global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, 
                                                             int64_t kp, int8_t* __restrict__ out) {
   const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
   if (c0 >= kp) return;
-  const int64_t plane = rows * kp;
+  const int64_t plane = plane_size(rows, kp);
   for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
     int64_t v[8];
     if (VEC && c0 + 8 <= cols) {
@@ -90,13 +100,13 @@ __global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, 
       for (int i = 0; i < D; i++) packed[i] |= (uint64_t)(uint8_t)d[i] << (8 * e);
     }
 #pragma unroll
-    for (int i = 0; i < D; i++) *(uint64_t*)(out + i * plane + r * kp + c0) = packed[i];
+    for (int i = 0; i < D; i++) *(uint64_t*)(out + i * plane + plane_at(r, c0, kp)) = packed[i];
   }
 }
 
-// B (krows x ncols, row-major, ld) -> transposed planes out[D][ncols][kp].
+// B (krows x ncols, row-major, ld) -> D transposed planes of ncols x kp.
 // 64 x 64 tiles through LDS so that both the reads (along n) and the writes
-// (along k) are contiguous.
+// (16 columns' 64 k-bytes, one whole block, per 256 threads) are contiguous.
 template <int D, class In>
 __global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows, int64_t ncols, int64_t ld,
                                                             int64_t kp, int8_t* __restrict__ out) {
@@ -124,7 +134,7 @@ __global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows,
   }
   __syncthreads();
   // write: for each plane and column, 64 k-bytes as 16 words
-  const int64_t plane = ncols * kp;
+  const int64_t plane = plane_size(ncols, kp);
 #pragma unroll
   for (int u = 0; u < 4 * D; u++) {  // D x 64 columns x 16 words over 256 threads
     const int e = tid + 256 * u;
@@ -133,7 +143,7 @@ __global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows,
     const int cn = rem / 16, w = rem % 16;
     const int64_t ocol = n0 + cn, kq = k0 + 4 * w;
     if (ocol < ncols && kq < kp)  // 4 digit bytes, k-order, read as one word (rows are 68 bytes)
-      *(uint32_t*)(out + i * plane + ocol * kp + kq) = *(const uint32_t*)&tile[i][cn][4 * w];
+      *(uint32_t*)(out + i * plane + plane_at(ocol, kq, kp)) = *(const uint32_t*)&tile[i][cn][4 * w];
   }
 }
 

@@ -65,8 +65,8 @@ __device__ __forceinline__ double addmod(double x, double y, double p) {
 }
 
 struct GemmArgs {
-  const int8_t* Ad;  // [D][m][kp]
-  const int8_t* Bd;  // [D][n][kp]
+  const int8_t* Ad;  // D planes of m x kp (16-row blocks, plane_at)
+  const int8_t* Bd;  // D planes of n x kp
   double* C;
   int64_t m, n, kp, ldc;
   double p, q;
@@ -118,7 +118,8 @@ struct I8Shape {
 };
 
 // Ring of NS LDS stages; each holds D digit planes of a BM x 64 slab of A
-// and of a BN x 64 slab of B^T, 64 bytes per row with no padding.  The four
+// and of a BN x 64 slab of B^T, 64 bytes per row with no padding (each 16-row
+// part is one 1 KB block of a plane, copied by one instruction).  The four
 // 16-byte chunks of row r are stored in the order q ^ f(r) with
 // f(r) = ((r >> 2) ^ (r >> 1)) & 3.  An operand read takes chunk q of 16
 // consecutive rows; f keeps those chunks in distinct banks whether the LDS
@@ -139,8 +140,8 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 // The digit-product loop of one BM x BN tile.  Stage st + 1's slabs are
-// copied from HBM straight into LDS (global_load_lds, 1 KB per wave
-// instruction) while stage st is multiplied: all D^2 digit products on
+// copied from HBM straight into LDS (global_load_lds, one contiguous 1 KB
+// block per wave instruction) while stage st is multiplied: all D^2 digit products on
 // 16x16x64 INT8 MFMAs into the 2D - 1 digit-weight accumulators.  fold()
 // runs after every stages_per_block stages and once at the end if the last
 // block is partial.  Rows and columns past the matrix edge read an in-range
@@ -160,15 +161,16 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
   static_assert(IPW < 64, "vmcnt range");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
-  const int64_t planeA = m * kp, planeB = n * kp;
+  const int64_t planeA = plane_size(m, kp), planeB = plane_size(n, kp);
   const int rl = lane >> 2;                       // row within a 16-row group
   const int ql = (lane & 3) ^ (((lane >> 4) ^ (lane >> 3)) & 3);  // chunk this lane copies: f(rl)
 
-  // Copies move 16 rows x 64 bytes of one digit plane straight into LDS
-  // (global_load_lds, 16 bytes a lane).  Each lane's byte offset within its
-  // plane (row rl of the copy's 16, chunk ql; rows past m or n read the last
-  // row instead, feeding outputs that are never stored) is fixed for the
-  // whole loop; only the plane's scalar base moves by 64 bytes a stage.  The
+  // Copies move one 1 KB block (16 rows x 64 bytes) of a digit plane
+  // straight into LDS (global_load_lds, 16 bytes a lane).  Each lane's byte
+  // offset within its plane (row rl of the copy's 16, chunk ql; rows past m
+  // or n read the last row instead, feeding outputs that are never stored)
+  // is fixed for the whole loop; only the plane's scalar base moves, by one
+  // block (1 KB) a stage.  The
   // wave index is made uniform once, so a copy's plane, base and LDS
   // destination are scalars and a stage's copies need no vector work.
   const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -180,10 +182,10 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
       voff[e] = 0;  // no copy
     } else if (t < D * BM / 16) {
       const int64_t row = m0 + 16 * (t % (BM / 16)) + rl;
-      voff[e] = (uint64_t)((row < m ? row : m - 1) * kp + 16 * ql);
+      voff[e] = (uint64_t)plane_at(row < m ? row : m - 1, 16 * ql, kp);
     } else {
       const int64_t row = n0 + 16 * ((t - D * BM / 16) % (BN / 16)) + rl;
-      voff[e] = (uint64_t)((row < n ? row : n - 1) * kp + 16 * ql);
+      voff[e] = (uint64_t)plane_at(row < n ? row : n - 1, 16 * ql, kp);
     }
   }
   // copies this wave issues per stage
@@ -198,12 +200,12 @@ __device__ __forceinline__ void digit_tile_loop(const int8_t* __restrict__ Ad, c
       if (t < D * BM / 16) {
         plane = t / (BM / 16);
         row0 = 16 * (t % (BM / 16));
-        base = Ad + plane * planeA + st * 64;
+        base = Ad + plane * planeA + st * 1024;
       } else {
         const int t2 = t - D * BM / 16;
         plane = t2 / (BN / 16);
         row0 = BM + 16 * (t2 % (BN / 16));
-        base = Bd + plane * planeB + st * 64;
+        base = Bd + plane * planeB + st * 1024;
       }
       __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
                                        (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
@@ -365,8 +367,8 @@ int8_digits_gemm_kernel(const GemmBatch bt) {
 // C_i = sum_s 256^s D_s mod p_i.
 constexpr int kMaxPrimes = 64;
 struct CrtArgs {
-  const int8_t* Ad;  // [D][m][kp]
-  const int8_t* Bd;  // [D][n][kp]
+  const int8_t* Ad;  // D planes of m x kp (16-row blocks, plane_at)
+  const int8_t* Bd;  // D planes of n x kp
   int64_t m, n, kp, ldc;
   int nprimes;
   double p[kMaxPrimes];

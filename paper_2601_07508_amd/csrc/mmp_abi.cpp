@@ -347,7 +347,7 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
 size_t mmp_operand_bytes(uint64_t p, int side, int64_t rows, int64_t cols) {
   if (p < 5 || p >= kPMax || (side != 0 && side != 1) || rows <= 0 || cols <= 0) return 0;
   const int64_t inner = side == 0 ? cols : rows, outer = side == 0 ? rows : cols;
-  return (size_t)digits_for(p) * (size_t)outer * (size_t)((inner + 63) / 64 * 64);
+  return digit_planes_bytes(digits_for(p), outer, (inner + 63) / 64 * 64);
 }
 
 int mmp_prepare_operand(uint64_t p, int side, const double* M, int64_t rows, int64_t cols, int64_t ld,

@@ -165,10 +165,10 @@ size_t mmp_workspace_crt(int64_t m, int64_t n, int64_t k, int entry_bits, int np
   if (m <= 0 || n <= 0 || k <= 0 || entry_bits < 1 || entry_bits > 62 || nprimes < 1) return 0;
   const int d = crt_digits(entry_bits);
   const size_t kp = (size_t)((k + 63) / 64 * 64);
-  if (crt_fast(k, d, nprimes)) return (size_t)d * (size_t)(m + n) * kp;
+  if (crt_fast(k, d, nprimes)) return digit_planes_bytes(d, m, kp) + digit_planes_bytes(d, n, kp);
   // fallback: per modulus, reduced A and B in binary64 (the products use the
-  // planner's form; an INT8 product needs at most 7 (m + n) kp more bytes)
-  const size_t per = align_up(8 * (size_t)(m * k + k * n)) + align_up(7 * (size_t)(m + n) * kp);
+  // planner's form; an INT8 product needs at most 7-digit planes of A and B)
+  const size_t per = align_up(8 * (size_t)(m * k + k * n)) + align_up(int8_workspace_bytes(kMaxDigits, m, n, k));
   return per * (size_t)nprimes;
 }
 
@@ -230,8 +230,7 @@ int mm_modp_crt(const mmp_opts* opts, const uint64_t* A, int64_t lda, const uint
       }
     } else {
       // reduce mod each p on the device, then the products as one batch
-      const size_t kp = (size_t)((k + 63) / 64 * 64);
-      const size_t per = align_up(8 * (size_t)(m * k + k * n)) + align_up(7 * (size_t)(m + n) * kp);
+      const size_t per = align_up(8 * (size_t)(m * k + k * n)) + align_up(int8_workspace_bytes(kMaxDigits, m, n, k));
       std::vector<mmp_job> jobs(nprimes);
       for (int i = 0; i < nprimes && st == MMP_OK; i++) {
         double* Ar = (double*)((char*)work + per * i);
@@ -258,7 +257,7 @@ int mm_modp_crt(const mmp_opts* opts, const uint64_t* A, int64_t lda, const uint
         if (opts) o.form = opts->form;
         o.splits = 1;
         o.workspace = (char*)work + per * i + align_up(8 * (size_t)(m * k + k * n));
-        o.workspace_bytes = align_up(7 * (size_t)(m + n) * kp);
+        o.workspace_bytes = align_up(int8_workspace_bytes(kMaxDigits, m, n, k));
         st = mm_modp_async(&o, jobs[i].p, 0, 0, m, n, k, jobs[i].A, jobs[i].lda, jobs[i].B, jobs[i].ldb,
                            jobs[i].C, jobs[i].ldc, stream);
       }

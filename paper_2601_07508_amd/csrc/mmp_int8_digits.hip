@@ -62,7 +62,7 @@ int MMP_CAT(launch_int8_digitize_, MMP_D)(const Int8Args& g, void* stream) {
   constexpr int D = MMP_D;
   // planes made here: A's (unless resident), then B's (unless resident)
   int8_t* Ad = g.work;
-  int8_t* Bd = g.work + (g.resident_a ? (size_t)0 : (size_t)D * g.m * g.kp);
+  int8_t* Bd = g.work + (g.resident_a ? (size_t)0 : digit_planes_bytes(D, g.m, g.kp));
   if (!g.resident_a)
     if (int e = MMP_CAT(launch_int8_digitize_side_, MMP_D)(0, g.A, g.m, g.k, g.lda, g.kp, g.p, Ad, stream)) return e;
   if (!g.resident_b)
@@ -84,7 +84,7 @@ int launch_gemm(const Int8Args* jobs, int njobs, hipStream_t s) {
     const Int8Args& g = jobs[j];
     GemmArgs& a = b.job[j];
     a.Ad = g.resident_a ? g.resident_a : g.work;
-    a.Bd = g.resident_b ? g.resident_b : g.work + (g.resident_a ? (size_t)0 : (size_t)D * g.m * g.kp);
+    a.Bd = g.resident_b ? g.resident_b : g.work + (g.resident_a ? (size_t)0 : digit_planes_bytes(D, g.m, g.kp));
     a.C = g.C;
     a.m = g.m;
     a.n = g.n;
@@ -130,7 +130,7 @@ int MMP_CAT(launch_crt_, MMP_D)(const CrtLaunch& c, void* stream) {
   if (c.nprimes < 1 || c.nprimes > kMaxPrimes) return (int)hipErrorInvalidValue;
   const int64_t kp = c.kp;
   int8_t* Ad = c.work;
-  int8_t* Bd = c.work + (size_t)D * c.m * kp;
+  int8_t* Bd = c.work + digit_planes_bytes(D, c.m, kp);
   {
     const IntegerIn in{c.A};
     TimerTok* t = timer_begin("crt_digitize_a");

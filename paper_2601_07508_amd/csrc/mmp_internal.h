@@ -108,6 +108,17 @@ struct Fp64Args {
 
 // INT8-digit form: digit planes in a device workspace, then the digit GEMM.
 constexpr int kMaxDigits = 7;  // signed base-256 digits cover p < 2^56
+// A digit plane of `rows` rows by kp k-bytes (kp a multiple of 64) is stored
+// in blocks of 16 rows by 64 k-bytes, 1 KB each, row-major inside a block:
+// byte (r, c) sits at (r / 16) 16 kp + (c / 64) 1024 + (r % 16) 64 + c % 64.
+// One block is what the digit GEMM copies into LDS in one instruction, and a
+// 16-row group's successive k-stages are contiguous.  A plane takes
+// plane_rows(rows) kp bytes; rows past `rows` in the last block are never
+// written or read.
+inline int64_t plane_rows(int64_t rows) { return (rows + 15) / 16 * 16; }
+inline size_t digit_planes_bytes(int digits, int64_t rows, int64_t kp) {
+  return (size_t)digits * (size_t)plane_rows(rows) * (size_t)kp;
+}
 struct Int8Args {
   const double* A;
   const double* B;
@@ -117,7 +128,7 @@ struct Int8Args {
   uint64_t p;
   double q;
   int64_t kblock;    // k-terms per int32 accumulation block (multiple of 64)
-  int8_t* work;      // D (m + n) kp bytes: planes of A, then of B^T
+  int8_t* work;      // planes of A (digit_planes_bytes(D, m, kp)), then of B^T
   const int8_t* resident_a;  // optional ready planes of A (then A is not digitised)
   const int8_t* resident_b;  // optional ready planes of B^T
   // work holds the planes made per call: A's (absent when resident), then B's
@@ -132,8 +143,8 @@ int choose_splits(int64_t tiles, int64_t stages, int64_t min_stages_per_split);
 int choose_splits_fill(int64_t tiles, int64_t stages, int64_t min_stages_per_split);  // INT8 digit GEMM
 // the planner's split-K for a plan (its form, tile and block) and shape
 int default_splits(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k);
-// Digit planes of one operand side into out (side 0: A rows -> [D][rows][kp];
-// side 1: B columns -> [D][cols][kp]).
+// Digit planes of one operand side into out (side 0: A's rows, D planes of
+// rows x kp; side 1: B's columns, D planes of cols x kp; blocked as above).
 int launch_int8_digitize_side(int digits, int side, const double* X, int64_t rows, int64_t cols, int64_t ld,
                               int64_t kp, uint64_t p, int8_t* out, void* stream);
 int digits_for(uint64_t p);                       // ceil(bitsize(p) / 8)
@@ -153,7 +164,7 @@ struct CrtLaunch {
   int nprimes;
   uint64_t p[kMaxPrimesCrt];
   double* C[kMaxPrimesCrt];
-  int8_t* work;  // digits (m + n) kp bytes
+  int8_t* work;  // planes of A, then of B^T (digit_planes_bytes each)
 };
 int crt_digits(int entry_bits);  // ceil((entry_bits + 1) / 8), signed digits of values < 2^entry_bits
 int launch_crt(int digits, const CrtLaunch& c, void* stream);

@@ -320,13 +320,13 @@ int64_t int8_kblock(int digits) {
 
 size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k) {
   const int64_t kp = cdiv(k, 64) * 64;
-  return (size_t)digits * (size_t)(m + n) * (size_t)kp;
+  return digit_planes_bytes(digits, m, kp) + digit_planes_bytes(digits, n, kp);
 }
 
 size_t int8_planes_bytes(int digits, int64_t m, int64_t n, int64_t k, bool res_a, bool res_b) {
-  const size_t kp = (size_t)(cdiv(k, 64) * 64);
-  const size_t rows = (res_a ? 0 : (size_t)m) + (res_b ? 0 : (size_t)n);
-  return ((size_t)digits * rows * kp + 255) / 256 * 256;
+  const int64_t kp = cdiv(k, 64) * 64;
+  const size_t bytes = (res_a ? 0 : digit_planes_bytes(digits, m, kp)) + (res_b ? 0 : digit_planes_bytes(digits, n, kp));
+  return (bytes + 255) / 256 * 256;
 }
 
 static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mmp_opts* opts,

@@ -46,7 +46,7 @@ struct Operand {
   const double* M;
   int64_t rows, cols, ld;
   uint64_t p;
-  int side;  // 0: an A (planes [D][rows][kp]), 1: a B (planes [D][cols][kp])
+  int side;  // 0: an A (D planes of rows x kp), 1: a B (D planes of cols x kp)
   int digits;
   int64_t kp;
   int8_t* planes;
@@ -386,7 +386,7 @@ int mmp_register_operand(mmp_server* s, const double* M, int64_t rows, int64_t c
     const int64_t kdim = side == 0 ? cols : rows;  // the inner dimension
     const int64_t outer = side == 0 ? rows : cols;
     o.kp = (kdim + 63) / 64 * 64;
-    o.bytes = (size_t)o.digits * (size_t)outer * (size_t)o.kp;
+    o.bytes = digit_planes_bytes(o.digits, outer, o.kp);
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->used + o.bytes > s->budget) return MMP_ENOMEM;
     if (int e = (int)hipSetDevice(s->device)) return hip_status(e);

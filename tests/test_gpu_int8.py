@@ -178,7 +178,9 @@ def test_prepared_operands(p):
         dA, dB = dev(A), dev(B)
         pa = mmp.prepare_operand(dA, p, 0)
         pb = mmp.prepare_operand(dB, p, 1)
-        assert pa.planes.numel() == pa.desc.digits * m * (-(-k // 64) * 64)
+        # digits x (m rounded up to 16) x (k rounded up to 64)
+        assert pa.planes.numel() == pa.desc.digits * (-(-m // 16) * 16) * (-(-k // 64) * 64)
+        assert pb.planes.numel() == pb.desc.digits * (-(-n // 16) * 16) * (-(-k // 64) * 64)
         for kw in ({"prepared_a": pa}, {"prepared_b": pb}, {"prepared_a": pa, "prepared_b": pb},
                    {"prepared_a": pa, "splits": 3}, {"prepared_b": pb, "force_kblock": 64}):
             say("prepared", p, m, n, k, sorted(kw))

@@ -214,15 +214,17 @@ def test_argument_errors_before_device_work():
 def test_prepared_operand_host_checks():
     lib = mmp.lib()
     p = 68719476731  # 36 bits: 5 digits
-    # digits x outer x (inner rounded up to 64)
-    assert lib.mmp_operand_bytes(p, 0, 10, 100) == 5 * 10 * 128
-    assert lib.mmp_operand_bytes(p, 1, 100, 10) == 5 * 10 * 128
-    assert lib.mmp_operand_bytes(p, 0, 3, 64) == 5 * 3 * 64
+    # digits x (outer rounded up to 16) x (inner rounded up to 64)
+    assert lib.mmp_operand_bytes(p, 0, 10, 100) == 5 * 16 * 128
+    assert lib.mmp_operand_bytes(p, 1, 100, 10) == 5 * 16 * 128
+    assert lib.mmp_operand_bytes(p, 0, 3, 64) == 5 * 16 * 64
+    assert lib.mmp_operand_bytes(p, 0, 32, 65) == 5 * 32 * 128
+    assert lib.mmp_operand_bytes(p, 1, 65, 33) == 5 * 48 * 128
     for bad in ((p, 2, 10, 10), (p, 0, 0, 10), (p, 1, 10, -1), (3, 0, 10, 10)):
         assert lib.mmp_operand_bytes(*bad) == 0
     fake, buf = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000)
     d = mmp.MmpOperand()
-    need = 5 * 10 * 128
+    need = 5 * 16 * 128
     # buffer too small, missing out, bad side, ld < cols: refused before any launch
     assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 100, buf, need - 1, ctypes.byref(d), None) == -1
     assert lib.mmp_prepare_operand(p, 0, fake, 10, 100, 100, buf, need, None, None) == -1
