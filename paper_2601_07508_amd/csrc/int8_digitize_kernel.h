@@ -70,18 +70,19 @@ struct IntegerIn {
 };
 
 // A (rows x cols, row-major, ld) -> D planes of rows x kp, k zero-padded to kp.
-// Grid: x over 2048-column chunks of a row, y over rows (strided).  Each
-// thread digitises 8 consecutive columns and stores one 8-byte word per plane
-// (a wave fills eight whole 64-byte block rows per plane).  VEC: the row's entries are
+// A workgroup covers 16 rows by 128 columns, two whole 1 KB blocks of every
+// plane: grid x over 128-column chunks, y over 16-row groups (strided).  Each
+// thread digitises 8 consecutive columns of one row (16 threads read 1 KB of
+// a row) and stores one 8-byte word per plane.  VEC: the row's entries are
 // 16-byte aligned (aligned base, even ld), so whole groups of 8 load as four
 // 16-byte vectors.
 template <int D, class In, bool VEC>
 __global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, int64_t cols, int64_t ld,
                                                             int64_t kp, int8_t* __restrict__ out) {
-  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+  const int64_t c0 = (int64_t)blockIdx.x * 128 + (threadIdx.x & 15) * 8;
   if (c0 >= kp) return;
   const int64_t plane = plane_size(rows, kp);
-  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+  for (int64_t r = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4); r < rows; r += (int64_t)gridDim.y * 16) {
     int64_t v[8];
     if (VEC && c0 + 8 <= cols) {
       X.load8(r * ld + c0, v);

@@ -12,13 +12,15 @@
 namespace mmp {
 
 namespace {
-// Row digitizing launch: x over 2048-column chunks, y over rows (strided
-// beyond 65535); the vector form when every row starts 16-byte aligned.
+// Row digitizing launch: x over 128-column chunks, y over 16-row groups
+// (strided beyond 65535); the vector form when every row starts 16-byte
+// aligned.
 template <int D, class In, class T>
 hipError_t launch_digitize_rows(const In& in, const T* X, int64_t rows, int64_t cols, int64_t ld, int64_t kp,
                                 int8_t* out, hipStream_t s, TimerTok* t) {
   if (rows <= 0 || kp <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((kp + 2047) / 2048), (unsigned)std::min<int64_t>(rows, 65535));
+  if ((kp + 127) / 128 > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((kp + 127) / 128), (unsigned)std::min<int64_t>((rows + 15) / 16, 65535));
   if (((uintptr_t)X % 16) == 0 && ld % 2 == 0)
     hipExtLaunchKernelGGL((i8d::digitize_rows_kernel<D, In, true>), grid, dim3(256), 0, s, timer_start(t),
                           timer_stop(t), 0, in, rows, cols, ld, kp, out);
@@ -31,8 +33,8 @@ hipError_t launch_digitize_rows(const In& in, const T* X, int64_t rows, int64_t 
 
 #if MMP_D <= 7  // residues of p < 2^52 need at most 7 digits
 
-// side 0: X is A (rows x cols = m x k) -> planes [D][m][kp];
-// side 1: X is B (rows x cols = k x n) -> transposed planes [D][n][kp].
+// side 0: X is A (rows x cols = m x k) -> D planes of m x kp;
+// side 1: X is B (rows x cols = k x n) -> D transposed planes of n x kp.
 int MMP_CAT(launch_int8_digitize_side_, MMP_D)(int side, const double* X, int64_t rows, int64_t cols, int64_t ld,
                                                int64_t kp, uint64_t p, int8_t* out, void* stream) {
   using namespace i8d;
