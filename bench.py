@@ -478,6 +478,8 @@ def main():
         work = 2.0 * plan["u"] * plan["v"] * mnk  # word flops per launch
     else:
         kernel, phase, peak, unit = "int8_digits_gemm_kernel", "int8_gemm", INT8_MFMA_PEAK_TOPS, "TOP/s"
+        if "int8_gemm_persistent" in phases:  # many short tiles: the persistent form of the digit GEMM
+            kernel, phase = "int8_digits_gemm_persistent_kernel", "int8_gemm_persistent"
         work = 2.0 * plan["digits_a"] * plan["digits_b"] * mnk  # digit-product int8 ops per launch
     launches, total_ms = phases.get(phase, (0, 0.0))
     kern_ms = total_ms / max(launches, 1)

@@ -1,6 +1,9 @@
 // One digit count D of the INT8-digit form, selected at build time by MMP_D:
 // the digitizing passes of one product and the digit GEMM of a batch.
+#include <atomic>
+
 #include "int8_digits_kernel.h"
+#include "int8_digits_persistent.h"
 
 #if !defined(MMP_D)
 #error "build with -DMMP_D=<digits>"
@@ -73,6 +76,24 @@ int MMP_CAT(launch_int8_digitize_, MMP_D)(const Int8Args& g, void* stream) {
 }
 
 namespace {
+i8d::GemmArgs gemm_args(const Int8Args& g) {
+  using namespace i8d;
+  GemmArgs a;
+  a.Ad = g.resident_a ? g.resident_a : g.work;
+  a.Bd = g.resident_b ? g.resident_b : g.work + (g.resident_a ? (size_t)0 : digit_planes_bytes(MMP_D, g.m, g.kp));
+  a.C = g.C;
+  a.m = g.m;
+  a.n = g.n;
+  a.kp = g.kp;
+  a.ldc = g.ldc;
+  a.p = (double)g.p;
+  a.q = g.q;
+  a.stages_per_block = g.kblock / kBK8;
+  a.splits = g.splits < 1 ? 1 : g.splits;
+  a.partial = g.partial;
+  return a;
+}
+
 template <bool NARROW>
 int launch_gemm(const Int8Args* jobs, int njobs, hipStream_t s) {
   using namespace i8d;
@@ -85,18 +106,7 @@ int launch_gemm(const Int8Args* jobs, int njobs, hipStream_t s) {
   for (int j = 0; j < njobs; j++) {
     const Int8Args& g = jobs[j];
     GemmArgs& a = b.job[j];
-    a.Ad = g.resident_a ? g.resident_a : g.work;
-    a.Bd = g.resident_b ? g.resident_b : g.work + (g.resident_a ? (size_t)0 : digit_planes_bytes(D, g.m, g.kp));
-    a.C = g.C;
-    a.m = g.m;
-    a.n = g.n;
-    a.kp = g.kp;
-    a.ldc = g.ldc;
-    a.p = (double)g.p;
-    a.q = g.q;
-    a.stages_per_block = g.kblock / kBK8;
-    a.splits = g.splits < 1 ? 1 : g.splits;
-    a.partial = g.partial;
+    a = gemm_args(g);
     b.tile_start[j] = (int)total;
     total += ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN) * a.splits;
     if (total > 0x7fffffff) return (int)hipErrorInvalidValue;
@@ -110,15 +120,75 @@ int launch_gemm(const Int8Args* jobs, int njobs, hipStream_t s) {
   timer_commit(t, e);
   return e;
 }
+// Workgroups of the persistent kernel the current device holds at once:
+// compute units x resident workgroups per unit (registers and LDS decide;
+// cached per device).
+template <int D>
+int64_t persistent_slots() {
+  static std::atomic<int64_t> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+  if (dev < 64) {
+    const int64_t c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, i8d::int8_digits_gemm_persistent_kernel<D>,
+                                                   i8d::I8Shape<D, false>::THREADS, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = i8d::I8Shape<D, false>::GROUPS_PER_CU;
+  const int64_t slots = (int64_t)cus * per_cu;
+  if (dev < 64) cache[dev].store(slots, std::memory_order_relaxed);
+  return slots;
+}
+
+// One product of 64 x 64 tiles whose tiles are short (at most
+// kPersistentMaxStages k-stages, whole k per tile, within one int32 block)
+// and at least twice as many as the device holds workgroups: the persistent
+// kernel, one workgroup per resident slot.
+constexpr int64_t kPersistentMaxStages = 16;
+// Not at 5 digits: there the persistent kernel's extra loop state does not
+// fit the 256 VGPRs of two waves per SIMD without spilling.
+int launch_persistent_if_short(const Int8Args& g, hipStream_t s, bool* launched) {
+  using namespace i8d;
+  constexpr int D = MMP_D;
+  using S = I8Shape<D, false>;
+  *launched = false;
+  if constexpr (D == 5) {
+    (void)g;
+    (void)s;
+    return 0;
+  } else {
+    if (g.splits > 1 || g.kp <= 0 || g.kp / kBK8 > kPersistentMaxStages || g.kp > g.kblock) return 0;
+    const int64_t tiles = ((g.m + S::BM - 1) / S::BM) * ((g.n + S::BN - 1) / S::BN);
+    const int64_t slots = persistent_slots<D>();
+    if (tiles < 2 * slots || tiles > 0x7fffffff) return 0;
+    const GemmArgs a = gemm_args(g);
+    *launched = true;
+    TimerTok* t = timer_begin("int8_gemm_persistent");
+    hipExtLaunchKernelGGL((int8_digits_gemm_persistent_kernel<D>), dim3((unsigned)slots), dim3(S::THREADS), 0, s,
+                          timer_start(t), timer_stop(t), 0, a);
+    const int e = (int)hipGetLastError();
+    timer_commit(t, e);
+    return e;
+  }
+}
 }  // namespace
 
-// 64 x 32 tiles when every product of the launch has n <= 32, else 64 x 64.
+// 64 x 32 tiles when every product of the launch has n <= 32, else 64 x 64
+// (a lone product of many short tiles on the persistent kernel).
 int MMP_CAT(launch_int8_gemm_, MMP_D)(const Int8Args* jobs, int njobs, void* stream) {
   if (njobs < 1 || njobs > kMaxBatch) return (int)hipErrorInvalidValue;
   bool narrow = true;
   for (int j = 0; j < njobs; j++) narrow = narrow && jobs[j].n <= 32;
-  return narrow ? launch_gemm<true>(jobs, njobs, (hipStream_t)stream)
-                : launch_gemm<false>(jobs, njobs, (hipStream_t)stream);
+  if (narrow) return launch_gemm<true>(jobs, njobs, (hipStream_t)stream);
+  if (njobs == 1) {
+    bool launched = false;
+    const int e = launch_persistent_if_short(jobs[0], (hipStream_t)stream, &launched);
+    if (launched) return e;
+  }
+  return launch_gemm<false>(jobs, njobs, (hipStream_t)stream);
 }
 
 #endif

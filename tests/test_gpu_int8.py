@@ -208,6 +208,33 @@ def test_prepared_operand_strided_and_reused():
         assert_exact(C.cpu().numpy(), oracle.mm_modp(p, Abig[:, :k], B))
 
 
+@pytest.mark.parametrize("p", [5, 251, 65521, 8388593, 2147483647, 68719476731, 281474976710597,
+                               4503599627370449])
+def test_int8_many_short_tiles(p):
+    # a lone product of at least 4160 output tiles of 64 x 64 with whole k in
+    # at most 16 k-stages, more than twice the workgroups the device holds at
+    # once: the persistent kernel (one workgroup per resident slot walking
+    # its tiles, the copy ring running across tiles) except at 5 digits;
+    # ragged m, n and k, k of one stage and of exactly 16.  Checked on
+    # sampled rows (every column) against the oracle.
+    rng = np.random.default_rng(11)
+    for (m, n, k) in ((4100, 4090, 300), (4160, 4096, 64), (4096, 4111, 1024), (8200, 2060, 17)):
+        A = gen.random_matrix(m + k, 1, m, k, p)
+        B = gen.random_matrix(m + k, 2, k, n, p)
+        rows = np.unique(np.concatenate([[0, 1, 63, 64, m // 2, m - 65, m - 64, m - 1],
+                                         rng.integers(0, m, 8)]))
+        say("many short tiles", p, m, n, k)
+        mmp.timers_enable(True)
+        mmp.timers_read(reset=True)
+        C = run(p, A, B)
+        t = mmp.timers_read(reset=True)
+        mmp.timers_enable(False)
+        persistent = (p.bit_length() + 7) // 8 != 5
+        assert t.get("int8_gemm_persistent", (0, 0))[0] == (1 if persistent else 0), t
+        assert t.get("int8_gemm", (0, 0))[0] == (0 if persistent else 1), t
+        assert_exact(C[rows], oracle.mm_modp(p, A[rows], B))
+
+
 @pytest.mark.parametrize("p", [251, 65521, 8388593, 2147483647, 68719476731, 281474976710597, 4503599627370449])
 def test_int8_narrow_columns(p):
     # n <= 32 runs 64 x 32 tiles: every digit count, ragged m and k, n at and
