@@ -1,0 +1,117 @@
+// Multi-modular product (Section 5.2's setting): one integer pair A, B
+// against many moduli.  The digit products of the integers are formed once
+// (k within one int32 block, digit loop of int8_digits_kernel.h) and every
+// modulus reduces the same digit-weight sums in the epilogue:
+//     C_i = sum_s 256^s D_s mod p_i.
+//
+// The weights do not depend on the modulus, so the epilogue first combines
+// them, once per output, into exact groups of three,
+//     G_j = D_3j + 256 D_3j+1 + 65536 D_3j+2,
+// |G_j| <= (2^31 - 1) 65793 < 2^47.01 (an integer, exact in binary64), and
+// each modulus then runs Horner's rule over the groups with the scale 2^24
+// (fold_groups): ceil((2D - 1) / 3) short reductions instead of 2D - 2.
+#pragma once
+#include "int8_digits_kernel.h"
+
+namespace mmp {
+namespace i8d {
+
+// Alg. 1 with the quotient rounded to nearest and no corrections: for an
+// integer x with |x| < 2^53, c = floor(fl(x q + 1/2)) and d = x - c p
+// (exact in one fma when |d| < 2^53).  With q = fl(1/p), fl(x q + 1/2) is
+// within |x / p| 2^-52 + 2^-54 of x / p + 1/2, so |d| <= p/2 + |x| 2^-52 +
+// p 2^-54.
+__device__ __forceinline__ double reduce_near(double x, double p, double q) {
+  return fma(-floor(fma(x, q, 0.5)), p, x);
+}
+
+// sum_j 2^24j g[j] mod p in [0, p) for integers |g[j]| < 2^47.01, p < 2^52:
+//   t = reduce_near(g[NG-1]); t = reduce_near(2^24 t) + reduce_near(g[j]),
+// j = NG-2 .. 0; one complete reduction ends it.  Each reduced group lies
+// within p/2 + 1 of zero (|g| 2^-52 < 2^-4.9).  If |t| <= T, then 2^24 t is
+// exact (a power of two), its reduction lies within p/2 + 2^-28 T + p 2^-54
+// of zero, and the new t within p + 2 + 2^-28 T: T = p (1 + 2^-27) + 2
+// holds at every step, below 2^53, so every step is exact.  The final
+// quotient floor(t q) is then within one of t / p, which one correction on
+// each side absorbs.
+template <int NG>
+__device__ __forceinline__ double fold_groups(const double (&g)[NG], double p, double q) {
+  double t = reduce_near(g[NG - 1], p, q);
+#pragma unroll
+  for (int j = NG - 2; j >= 0; j--) t = reduce_near(16777216.0 * t, p, q) + reduce_near(g[j], p, q);
+  return fmod_full(t, p, q);
+}
+
+constexpr int kMaxPrimes = 64;
+struct CrtArgs {
+  const int8_t* Ad;  // D planes of m x kp (16-row blocks, plane_at)
+  const int8_t* Bd;  // D planes of n x kp
+  int64_t m, n, kp, ldc;
+  int nprimes;
+  double p[kMaxPrimes];
+  double q[kMaxPrimes];
+  double* C[kMaxPrimes];
+};
+
+template <int D>
+__global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) void crt_gemm_kernel(
+    const CrtArgs a) {
+  using S = I8Shape<D>;
+  constexpr int ND = 2 * D - 1;
+  constexpr int NG = (ND + 2) / 3;
+  constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
+  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN, S::STAGES> sm;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
+  const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
+  int tmi, tni;
+  tile_coords(blockIdx.x, nbm * nbn, nbm, nbn, tmi, tni);
+  const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
+
+  int4v acc[ND][TM][TN];
+#pragma unroll
+  for (int s = 0; s < ND; s++)
+#pragma unroll
+    for (int x = 0; x < TM; x++)
+#pragma unroll
+      for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
+  // one int32 block covers the whole k (checked by the launcher)
+  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, 0, a.kp / kBK8, a.kp / kBK8 + 1, sm, acc, [] {});
+
+  // the weights in exact groups of three, shared by every modulus
+  double g[TM][TN][4][NG];
+#pragma unroll
+  for (int x = 0; x < TM; x++)
+#pragma unroll
+    for (int y = 0; y < TN; y++)
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int j = 0; j < NG; j++) {
+          double v = (double)acc[3 * j][x][y][r];
+          if (3 * j + 1 < ND) v = fma(256.0, (double)acc[3 * j + 1][x][y][r], v);
+          if (3 * j + 2 < ND) v = fma(65536.0, (double)acc[3 * j + 2][x][y][r], v);
+          g[x][y][r][j] = v;
+        }
+
+  const int lrow = lane & 15;
+  for (int pi = 0; pi < a.nprimes; pi++) {
+    const double p = a.p[pi], q = a.q[pi];
+    double* C = a.C[pi];
+#pragma unroll
+    for (int x = 0; x < TM; x++)
+#pragma unroll
+      for (int y = 0; y < TN; y++) {
+        const int64_t col = n0 + wn + y * 16 + lrow;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const double t = fold_groups<NG>(g[x][y][r], p, q);
+          const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
+          if (row < a.m && col < a.n) C[row * a.ldc + col] = t + 0.0;
+        }
+      }
+  }
+}
+
+}  // namespace i8d
+}  // namespace mmp

@@ -361,66 +361,5 @@ int8_digits_gemm_kernel(const GemmBatch bt) {
     }
 }
 
-// Multi-modular product: one integer pair A, B against many moduli.  The
-// digit products of the integers are formed once (k within one int32 block)
-// and every modulus reduces the same digit-weight sums in the epilogue:
-// C_i = sum_s 256^s D_s mod p_i.
-constexpr int kMaxPrimes = 64;
-struct CrtArgs {
-  const int8_t* Ad;  // D planes of m x kp (16-row blocks, plane_at)
-  const int8_t* Bd;  // D planes of n x kp
-  int64_t m, n, kp, ldc;
-  int nprimes;
-  double p[kMaxPrimes];
-  double q[kMaxPrimes];
-  double* C[kMaxPrimes];
-};
-
-template <int D>
-__global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) void crt_gemm_kernel(
-    const CrtArgs a) {
-  using S = I8Shape<D>;
-  constexpr int ND = 2 * D - 1;
-  constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
-  __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN, S::STAGES> sm;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
-  const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
-  int tmi, tni;
-  tile_coords(blockIdx.x, nbm * nbn, nbm, nbn, tmi, tni);
-  const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
-
-  int4v acc[ND][TM][TN];
-#pragma unroll
-  for (int s = 0; s < ND; s++)
-#pragma unroll
-    for (int x = 0; x < TM; x++)
-#pragma unroll
-      for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
-  // one int32 block covers the whole k (checked by the launcher)
-  digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, 0, a.kp / kBK8, a.kp / kBK8 + 1, sm, acc, [] {});
-
-  const int lrow = lane & 15;
-  for (int pi = 0; pi < a.nprimes; pi++) {
-    const double p = a.p[pi], q = a.q[pi];
-    double* C = a.C[pi];
-#pragma unroll
-    for (int x = 0; x < TM; x++)
-#pragma unroll
-      for (int y = 0; y < TN; y++) {
-        const int64_t col = n0 + wn + y * 16 + lrow;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-          int w[ND];
-#pragma unroll
-          for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
-          const double t = fold_weights<ND>(w, p, q);
-          const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
-          if (row < a.m && col < a.n) C[row * a.ldc + col] = t + 0.0;
-        }
-      }
-  }
-}
-
 }  // namespace i8d
 }  // namespace mmp

@@ -2,6 +2,7 @@
 // the digitizing passes of one product and the digit GEMM of a batch.
 #include <atomic>
 
+#include "int8_crt_kernel.h"
 #include "int8_digits_kernel.h"
 #include "int8_digits_persistent.h"
 

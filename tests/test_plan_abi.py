@@ -665,6 +665,70 @@ def test_int8_fold_exact(p):
             assert _fold_weights(w, p) == want
 
 
+# The multi-modular (CRT) epilogue combines the weights once into exact
+# groups of three, G_j = w[3j] + 256 w[3j+1] + 65536 w[3j+2], and folds them
+# per modulus by Horner's rule with the scale 2^24, each step
+# t <- (2^24 t - c p) + (G_j - c_j p) with round-to-nearest quotients.
+# Emulated step by step in binary64 (pa.fma rounds once): every
+# intermediate must be exact and within the bounds the kernel's comment
+# derives, and the result must be sum 256^s w[s] mod p.
+
+
+def _reduce_near(x, p, q):
+    assert x == int(x) and abs(x) < 2.0 ** 80
+    c = math.floor(pa.fma(x, q, 0.5))
+    d = int(x) - c * p  # the fma's exact result when representable
+    assert abs(d) < 2 ** 53 and float(d) == d
+    return d
+
+
+def _fold_groups(w, p):
+    q = 1.0 / p
+    nd = len(w)
+    g = []
+    for j in range((nd + 2) // 3):
+        v = float(w[3 * j])
+        if 3 * j + 1 < nd:
+            v = pa.fma(256.0, float(w[3 * j + 1]), v)
+        if 3 * j + 2 < nd:
+            v = pa.fma(65536.0, float(w[3 * j + 2]), v)
+        exact = sum(256 ** i * w[3 * j + i] for i in range(3) if 3 * j + i < nd)
+        assert v == exact and abs(exact) < 2 ** 47.01
+        g.append(v)
+    bound = p * (1 + 2.0 ** -27) + 2
+    t = _reduce_near(g[-1], p, q)
+    assert abs(t) <= p / 2 + 1
+    for j in range(len(g) - 2, -1, -1):
+        x = 16777216.0 * float(t)
+        assert x == 2 ** 24 * t
+        r = _reduce_near(g[j], p, q)
+        assert abs(r) <= p / 2 + 1
+        t = _reduce_near(x, p, q) + r
+        assert abs(t) <= bound and abs(t) < 2 ** 53
+    c = math.floor(float(t) * q)
+    d = t - c * p
+    d = d - p if d >= p else d
+    d = d + p if d < 0 else d
+    assert 0 <= d < p
+    return d
+
+
+@pytest.mark.parametrize("p", [5, 7, 257, 1048573, 2147483647, 68719476731, 1125899906842597,
+                               4503599627370449, 2 ** 52 - 1])
+def test_crt_group_fold_exact(p):
+    # any modulus 5 <= p < 2^52 (the last one is not prime: the fold does not care)
+    lim = 2 ** 31 - 1
+    rng = gen.uniform_mod(p % 1000, 92, 3000, 2 * lim + 1)
+    vals = [int(x) - lim for x in rng]
+    for nd in (1, 2, 3, 4, 5, 7, 9, 13, 15):
+        cases = [[lim] * nd, [-lim] * nd, [lim, -lim] * (nd // 2) + [lim] * (nd % 2),
+                 [-lim, lim] * (nd // 2) + [-lim] * (nd % 2), [0] * nd]
+        cases += [vals[i * nd:(i + 1) * nd] for i in range(len(vals) // nd)][:40]
+        for w in cases:
+            want = sum(256 ** s * ws for s, ws in enumerate(w)) % p
+            assert _fold_groups(w, p) == want
+
+
 @pytest.mark.parametrize("shape", [(512, 512, 131072), (16384, 16384, 256), (4096, 4096, 4096), (64, 64, 1 << 20),
                                    (1000, 30, 50000), (10923, 32, 32768), (1024, 1024, 65536), (256, 2048, 65536)])
 @pytest.mark.parametrize("form", [1, 2])
