@@ -41,9 +41,11 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
   const int rl = lane >> 2;                                       // row within a 16-row group
   const int ql = (lane & 3) ^ (((lane >> 4) ^ (lane >> 3)) & 3);  // chunk this lane copies
 
-  // Copy offsets of the tile whose stages are being issued (see
-  // digit_tile_loop): one 1 KB block of a plane per copy, rows past m or n
-  // clamped to the last row.
+  // Copy offsets of the tile whose stages are being issued: one 1 KB block
+  // of a plane per copy, rows past m or n clamped to the last row.  The same
+  // copies as digit_tile_loop's, written out again here: routing both
+  // through one shared helper changed the code the compiler generates for
+  // the main digit GEMM (a longer loop), which this form must not touch.
   uint64_t voff[IPW];
   auto set_offsets = [&](int64_t m0, int64_t n0) {
 #pragma unroll
