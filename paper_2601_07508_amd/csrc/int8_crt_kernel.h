@@ -11,36 +11,10 @@
 // each modulus then runs Horner's rule over the groups with the scale 2^24
 // (fold_groups): ceil((2D - 1) / 3) short reductions instead of 2D - 2.
 #pragma once
-#include "int8_digits_kernel.h"
+#include "int8_fold.h"
 
 namespace mmp {
 namespace i8d {
-
-// Alg. 1 with the quotient rounded to nearest and no corrections: for an
-// integer x with |x| < 2^53, c = floor(fl(x q + 1/2)) and d = x - c p
-// (exact in one fma when |d| < 2^53).  With q = fl(1/p), fl(x q + 1/2) is
-// within |x / p| 2^-52 + 2^-54 of x / p + 1/2, so |d| <= p/2 + |x| 2^-52 +
-// p 2^-54.
-__device__ __forceinline__ double reduce_near(double x, double p, double q) {
-  return fma(-floor(fma(x, q, 0.5)), p, x);
-}
-
-// sum_j 2^24j g[j] mod p in [0, p) for integers |g[j]| < 2^47.01, p < 2^52:
-//   t = reduce_near(g[NG-1]); t = reduce_near(2^24 t) + reduce_near(g[j]),
-// j = NG-2 .. 0; one complete reduction ends it.  Each reduced group lies
-// within p/2 + 1 of zero (|g| 2^-52 < 2^-4.9).  If |t| <= T, then 2^24 t is
-// exact (a power of two), its reduction lies within p/2 + 2^-28 T + p 2^-54
-// of zero, and the new t within p + 2 + 2^-28 T: T = p (1 + 2^-27) + 2
-// holds at every step, below 2^53, so every step is exact.  The final
-// quotient floor(t q) is then within one of t / p, which one correction on
-// each side absorbs.
-template <int NG>
-__device__ __forceinline__ double fold_groups(const double (&g)[NG], double p, double q) {
-  double t = reduce_near(g[NG - 1], p, q);
-#pragma unroll
-  for (int j = NG - 2; j >= 0; j--) t = reduce_near(16777216.0 * t, p, q) + reduce_near(g[j], p, q);
-  return fmod_full(t, p, q);
-}
 
 constexpr int kMaxPrimes = 64;
 struct CrtArgs {
@@ -85,14 +59,13 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
 #pragma unroll
     for (int y = 0; y < TN; y++)
 #pragma unroll
-      for (int r = 0; r < 4; r++)
+      for (int r = 0; r < 4; r++) {
+        int w[ND];
 #pragma unroll
-        for (int j = 0; j < NG; j++) {
-          double v = (double)acc[3 * j][x][y][r];
-          if (3 * j + 1 < ND) v = fma(256.0, (double)acc[3 * j + 1][x][y][r], v);
-          if (3 * j + 2 < ND) v = fma(65536.0, (double)acc[3 * j + 2][x][y][r], v);
-          g[x][y][r][j] = v;
-        }
+        for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
+#pragma unroll
+        for (int j = 0; j < NG; j++) g[x][y][r][j] = weight_group<ND>(w, j);
+      }
 
   const int lrow = lane & 15;
   for (int pi = 0; pi < a.nprimes; pi++) {

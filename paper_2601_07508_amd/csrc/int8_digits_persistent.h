@@ -10,9 +10,10 @@
 // current tile's last stage is multiplied, folded and stored.  The digit
 // products, fold and output are those of int8_digits_gemm_kernel, whole k
 // per tile (no split-K) within one exact int32 block, so each tile folds
-// once, at its end, straight into C.
+// once, at its end, straight into C; from three digits on (p >= 2^16) with
+// fold_short, which the tiles' short k (at most 1024 terms) allows.
 #pragma once
-#include "int8_digits_kernel.h"
+#include "int8_fold.h"
 
 namespace mmp {
 namespace i8d {
@@ -162,7 +163,11 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
           int w[ND];
 #pragma unroll
           for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
-          const double t = fold_weights<ND>(w, p, q);
+          double t;
+          if constexpr (D >= 3)
+            t = fold_short<ND>(w, p, q);
+          else
+            t = fold_weights<ND>(w, p, q);
           const int64_t row = (int64_t)tmi * BM + wm + x * 16 + (lane >> 4) * 4 + r;
           if (row < a.m && col < a.n) a.C[row * a.ldc + col] = t + 0.0;
         }

@@ -1,0 +1,65 @@
+// Folds of digit-weight sums in groups of three (the INT8-digit form's
+// int32 accumulators D_s, value sum_s 256^s D_s): the multi-modular
+// epilogue's (int8_crt_kernel.h) and the short-tile fold of the persistent
+// digit GEMM (int8_digits_persistent.h).  All steps are Section 2.1's
+// binary64 arithmetic with exact results; each bound is stated where used.
+#pragma once
+#include "int8_digits_kernel.h"
+
+namespace mmp {
+namespace i8d {
+
+// G_j = D_3j + 256 D_3j+1 + 65536 D_3j+2 (missing terms zero), exact for
+// |D_s| < 2^31: |G_j| < 2^31 65793 < 2^47.01.
+template <int ND>
+__device__ __forceinline__ double weight_group(const int (&w)[ND], int j) {
+  double v = (double)w[3 * j];
+  if (3 * j + 1 < ND) v = fma(256.0, (double)w[3 * j + 1], v);
+  if (3 * j + 2 < ND) v = fma(65536.0, (double)w[3 * j + 2], v);
+  return v;
+}
+
+// Alg. 1 with the quotient rounded to nearest and no corrections: for an
+// integer x with |x| < 2^53, c = floor(fl(x q + 1/2)) and d = x - c p
+// (exact in one fma when |d| < 2^53).  With q = fl(1/p), fl(x q + 1/2) is
+// within |x / p| 2^-52 + 2^-54 of x / p + 1/2, so |d| <= p/2 + |x| 2^-52 +
+// p 2^-54.
+__device__ __forceinline__ double reduce_near(double x, double p, double q) {
+  return fma(-floor(fma(x, q, 0.5)), p, x);
+}
+
+// sum_j 2^24j g[j] mod p in [0, p) for integers |g[j]| < 2^47.01, p < 2^52:
+//   t = reduce_near(g[NG-1]); t = reduce_near(2^24 t) + reduce_near(g[j]),
+// j = NG-2 .. 0; one complete reduction ends it.  Each reduced group lies
+// within p/2 + 1 of zero (|g| 2^-52 < 2^-4.9).  If |t| <= T, then 2^24 t is
+// exact (a power of two), its reduction lies within p/2 + 2^-28 T + p 2^-54
+// of zero, and the new t within p + 2 + 2^-28 T: T = p (1 + 2^-27) + 2
+// holds at every step, below 2^53, so every step is exact.  The final
+// quotient floor(t q) is then within one of t / p, which one correction on
+// each side absorbs.
+template <int NG>
+__device__ __forceinline__ double fold_groups(const double (&g)[NG], double p, double q) {
+  double t = reduce_near(g[NG - 1], p, q);
+#pragma unroll
+  for (int j = NG - 2; j >= 0; j--) t = reduce_near(16777216.0 * t, p, q) + reduce_near(g[j], p, q);
+  return fmod_full(t, p, q);
+}
+
+// sum_s 256^s w[s] mod p in [0, p) for a tile whose whole k is at most
+// 1024 terms of D <= 7 digits and p >= 2^16 (three or more digits): then
+// |w[s]| <= 1024 * 7 * 2^14 < 2^26.81 and each group |G| < 2^42.82, and
+// Horner's rule runs over the groups directly, t = reduce_near(2^24 t) + G_j
+// from t = G_top.  The quotient argument stays below 2^24 + 2^42.82 / p <=
+// 2^51, so each reduction lies within p of zero (|e| < 0.45) and |t| <= p +
+// 2^42.82 < 2^53: every step is exact, and one complete reduction ends it.
+template <int ND>
+__device__ __forceinline__ double fold_short(const int (&w)[ND], double p, double q) {
+  constexpr int NG = (ND + 2) / 3;
+  double t = weight_group<ND>(w, NG - 1);
+#pragma unroll
+  for (int j = NG - 2; j >= 0; j--) t = reduce_near(16777216.0 * t, p, q) + weight_group<ND>(w, j);
+  return fmod_full(t, p, q);
+}
+
+}  // namespace i8d
+}  // namespace mmp

@@ -729,6 +729,56 @@ def test_crt_group_fold_exact(p):
             assert _fold_groups(w, p) == want
 
 
+# The persistent digit GEMM's tiles have whole k in at most 1024 terms, so
+# every weight is within 1024 * 7 * 2^14 of zero; from three digits on
+# (p >= 2^16) they fold by Horner's rule directly over the unreduced groups
+# of three, t <- (2^24 t - c p) + G_j from t = G_top.  Emulated step by step.
+
+
+def _fold_short(w, p):
+    q = 1.0 / p
+    nd = len(w)
+    g = []
+    for j in range((nd + 2) // 3):
+        v = float(w[3 * j])
+        if 3 * j + 1 < nd:
+            v = pa.fma(256.0, float(w[3 * j + 1]), v)
+        if 3 * j + 2 < nd:
+            v = pa.fma(65536.0, float(w[3 * j + 2]), v)
+        exact = sum(256 ** i * w[3 * j + i] for i in range(3) if 3 * j + i < nd)
+        assert v == exact and abs(exact) < 2 ** 42.82
+        g.append(exact)
+    t = g[-1]
+    for j in range(len(g) - 2, -1, -1):
+        x = 16777216.0 * float(t)
+        assert x == 2 ** 24 * t and abs(x / p) <= 2 ** 51
+        d = _reduce_near(x, p, q)
+        assert abs(d) < p
+        t = d + g[j]
+        assert abs(t) <= p + 2 ** 42.82 and abs(t) < 2 ** 53
+    c = math.floor(float(t) * q)
+    d = t - c * p
+    d = d - p if d >= p else d
+    d = d + p if d < 0 else d
+    assert 0 <= d < p
+    return d
+
+
+@pytest.mark.parametrize("p", [65537, 16777213, 2147483647, 68719476731, 1125899906842597,
+                               4503599627370449, 2 ** 16, 2 ** 52 - 1])
+def test_short_tile_fold_exact(p):
+    lim = 1024 * 7 * 2 ** 14  # 1024 k-terms of at most 7 digit products of |d| <= 128
+    rng = gen.uniform_mod(p % 1000, 93, 3000, 2 * lim + 1)
+    vals = [int(x) - lim for x in rng]
+    for nd in (5, 7, 9, 11, 13):
+        cases = [[lim] * nd, [-lim] * nd, [lim, -lim] * (nd // 2) + [lim] * (nd % 2),
+                 [-lim, lim] * (nd // 2) + [-lim] * (nd % 2), [0] * nd, [lim] + [0] * (nd - 1)]
+        cases += [vals[i * nd:(i + 1) * nd] for i in range(len(vals) // nd)][:40]
+        for w in cases:
+            want = sum(256 ** s * ws for s, ws in enumerate(w)) % p
+            assert _fold_short(w, p) == want
+
+
 @pytest.mark.parametrize("shape", [(512, 512, 131072), (16384, 16384, 256), (4096, 4096, 4096), (64, 64, 1 << 20),
                                    (1000, 30, 50000), (10923, 32, 32768), (1024, 1024, 65536), (256, 2048, 65536)])
 @pytest.mark.parametrize("form", [1, 2])
