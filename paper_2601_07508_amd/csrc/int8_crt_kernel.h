@@ -8,8 +8,11 @@
 // them, once per output, into exact groups of three,
 //     G_j = D_3j + 256 D_3j+1 + 65536 D_3j+2,
 // |G_j| <= (2^31 - 1) 65793 < 2^47.01 (an integer, exact in binary64), and
-// each modulus then runs Horner's rule over the groups with the scale 2^24
-// (fold_groups): ceil((2D - 1) / 3) short reductions instead of 2D - 2.
+// each modulus then runs Horner's rule over the groups with the scale 2^24:
+// ceil((2D - 1) / 3) - 1 steps instead of 2D - 2, over the groups as they
+// are when every modulus of the launch is large next to them (fold_direct;
+// the launcher checks Gmax <= (2^27 - 2) p), else over the groups each
+// reduced first (fold_groups).
 #pragma once
 #include "int8_fold.h"
 
@@ -22,6 +25,7 @@ struct CrtArgs {
   const int8_t* Bd;  // D planes of n x kp
   int64_t m, n, kp, ldc;
   int nprimes;
+  int direct;  // every modulus allows fold_direct for these groups
   double p[kMaxPrimes];
   double q[kMaxPrimes];
   double* C[kMaxPrimes];
@@ -78,7 +82,7 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
         const int64_t col = n0 + wn + y * 16 + lrow;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          const double t = fold_groups<NG>(g[x][y][r], p, q);
+          const double t = a.direct ? fold_direct<NG>(g[x][y][r], p, q) : fold_groups<NG>(g[x][y][r], p, q);
           const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
           if (row < a.m && col < a.n) C[row * a.ldc + col] = t + 0.0;
         }

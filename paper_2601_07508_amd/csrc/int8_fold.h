@@ -45,20 +45,33 @@ __device__ __forceinline__ double fold_groups(const double (&g)[NG], double p, d
   return fmod_full(t, p, q);
 }
 
-// sum_s 256^s w[s] mod p in [0, p) for a tile whose whole k is at most
-// 1024 terms of D <= 7 digits and p >= 2^16 (three or more digits): then
-// |w[s]| <= 1024 * 7 * 2^14 < 2^26.81 and each group |G| < 2^42.82, and
-// Horner's rule runs over the groups directly, t = reduce_near(2^24 t) + G_j
-// from t = G_top.  The quotient argument stays below 2^24 + 2^42.82 / p <=
-// 2^51, so each reduction lies within p of zero (|e| < 0.45) and |t| <= p +
-// 2^42.82 < 2^53: every step is exact, and one complete reduction ends it.
+// sum_j 2^24j g[j] mod p in [0, p) when the groups are small next to p:
+// |g[j]| <= Gmax with Gmax <= (2^27 - 2) p (and Gmax < 2^47.01, p < 2^52).
+// Horner's rule then runs over the groups directly, t = reduce_near(2^24 t)
+// + g[j] from t = g[NG-1], with no reduction of the groups themselves.  If
+// |t| <= p + Gmax, the quotient argument |2^24 t / p| <= 2^24 (1 + Gmax / p)
+// < 2^51, so its error is below 1/2, the reduction lies within p of zero
+// and the new |t| <= p + Gmax again (below 2^53): every step is exact, and
+// one complete reduction ends it.  For digit-weight sums over K k-terms of
+// D-digit operands, Gmax = 65793 K D 2^14 (direct_fold_ok).
+template <int NG>
+__device__ __forceinline__ double fold_direct(const double (&g)[NG], double p, double q) {
+  double t = g[NG - 1];
+#pragma unroll
+  for (int j = NG - 2; j >= 0; j--) t = reduce_near(16777216.0 * t, p, q) + g[j];
+  return fmod_full(t, p, q);
+}
+
+// The persistent digit GEMM's tiles: whole k at most 1024 terms, D <= 7 and
+// p >= 2^16 (three or more digits), so Gmax = 65793 * 1024 * 7 * 2^14 <
+// 2^42.82 <= 2^26.82 p: fold_direct over the groups of w.
 template <int ND>
 __device__ __forceinline__ double fold_short(const int (&w)[ND], double p, double q) {
   constexpr int NG = (ND + 2) / 3;
-  double t = weight_group<ND>(w, NG - 1);
+  double g[NG];
 #pragma unroll
-  for (int j = NG - 2; j >= 0; j--) t = reduce_near(16777216.0 * t, p, q) + weight_group<ND>(w, j);
-  return fmod_full(t, p, q);
+  for (int j = 0; j < NG; j++) g[j] = weight_group<ND>(w, j);
+  return fold_direct<NG>(g, p, q);
 }
 
 }  // namespace i8d

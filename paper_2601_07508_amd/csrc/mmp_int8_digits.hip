@@ -230,10 +230,15 @@ int MMP_CAT(launch_crt_, MMP_D)(const CrtLaunch& c, void* stream) {
   a.kp = kp;
   a.ldc = c.ldc;
   a.nprimes = c.nprimes;
+  // fold_direct's condition: Gmax = 65793 kp D 2^14 <= (2^27 - 2) p for
+  // every modulus (exact in 128-bit integers)
+  const unsigned __int128 gmax = (unsigned __int128)65793 * (uint64_t)kp * (uint64_t)D * 16384u;
+  a.direct = 1;
   for (int i = 0; i < c.nprimes; i++) {
     a.p[i] = (double)c.p[i];
     a.q[i] = 1.0 / (double)c.p[i];
     a.C[i] = c.C[i];
+    if (gmax > (unsigned __int128)((1ull << 27) - 2) * c.p[i]) a.direct = 0;
   }
   const int64_t nb = ((c.m + BM - 1) / BM) * ((c.n + BN - 1) / BN);
   if (nb <= 0) return 0;

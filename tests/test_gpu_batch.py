@@ -123,14 +123,19 @@ def test_crt_fast_path(bits, shape):
     _crt_check(A, B, primes, outs, bits)
 
 
-def test_crt_extreme_entries():
+# With p = 5 in the launch the epilogue reduces every group of three digit
+# weights first; when every modulus is at least 65793 k D 2^14 / (2^27 - 2)
+# (8225 here: k = 128, D = 8) it folds the groups directly.
+@pytest.mark.parametrize("primes", [[4503599627370449, 1125899906842597, 2147483647, 5],
+                                    [4503599627370449, 1125899906842597, 2147483647, 8231]])
+def test_crt_extreme_entries(primes):
     bits = 62
     m, n, k = 16, 16, 128
     top = (1 << bits) - 1
     vals = np.array([top, 0, top - 1, 1 << 61, (1 << 61) - 1, 0x7F7F7F7F7F7F7F7F & top], dtype=np.uint64)
     A = vals[np.arange(m * k) % len(vals)].reshape(m, k)
     B = vals[(np.arange(k * n) * 5 + 1) % len(vals)].reshape(k, n)
-    primes = [4503599627370449, 1125899906842597, 2147483647, 5]
+    assert all(gen.is_prime(p) for p in primes)
     outs = [torch.empty((m, n), dtype=torch.float64, device="cuda") for _ in primes]
     mmp.mm_modp_crt(dev64(A), dev64(B), primes, outs, bits)
     torch.cuda.synchronize()

@@ -729,15 +729,18 @@ def test_crt_group_fold_exact(p):
             assert _fold_groups(w, p) == want
 
 
-# The persistent digit GEMM's tiles have whole k in at most 1024 terms, so
-# every weight is within 1024 * 7 * 2^14 of zero; from three digits on
-# (p >= 2^16) they fold by Horner's rule directly over the unreduced groups
-# of three, t <- (2^24 t - c p) + G_j from t = G_top.  Emulated step by step.
+# When the groups are small next to p (Gmax <= (2^27 - 2) p, Gmax = 65793 K
+# D 2^14 for K k-terms of D digits), Horner's rule runs over the unreduced
+# groups directly, t <- (2^24 t - c p) + G_j from t = G_top: the persistent
+# digit GEMM's short tiles (K <= 1024, D <= 7, p >= 2^16) and the CRT
+# epilogue when every modulus of the launch allows it.  Emulated step by
+# step at the extreme weights, at and above the smallest modulus allowed.
 
 
-def _fold_short(w, p):
+def _fold_direct(w, p, gmax):
     q = 1.0 / p
     nd = len(w)
+    assert gmax <= (2 ** 27 - 2) * p
     g = []
     for j in range((nd + 2) // 3):
         v = float(w[3 * j])
@@ -746,16 +749,16 @@ def _fold_short(w, p):
         if 3 * j + 2 < nd:
             v = pa.fma(65536.0, float(w[3 * j + 2]), v)
         exact = sum(256 ** i * w[3 * j + i] for i in range(3) if 3 * j + i < nd)
-        assert v == exact and abs(exact) < 2 ** 42.82
+        assert v == exact and abs(exact) <= gmax
         g.append(exact)
     t = g[-1]
     for j in range(len(g) - 2, -1, -1):
         x = 16777216.0 * float(t)
-        assert x == 2 ** 24 * t and abs(x / p) <= 2 ** 51
+        assert x == 2 ** 24 * t and abs(x / p) < 2 ** 51
         d = _reduce_near(x, p, q)
         assert abs(d) < p
         t = d + g[j]
-        assert abs(t) <= p + 2 ** 42.82 and abs(t) < 2 ** 53
+        assert abs(t) <= p + gmax and abs(t) < 2 ** 53
     c = math.floor(float(t) * q)
     d = t - c * p
     d = d - p if d >= p else d
@@ -764,19 +767,37 @@ def _fold_short(w, p):
     return d
 
 
+def _direct_cases(p, W, seed):
+    rng = gen.uniform_mod(p % 1000, seed, 3000, 2 * W + 1)
+    vals = [int(x) - W for x in rng]
+    for nd in (5, 7, 9, 11, 13, 15):
+        cases = [[W] * nd, [-W] * nd, [W, -W] * (nd // 2) + [W] * (nd % 2),
+                 [-W, W] * (nd // 2) + [-W] * (nd % 2), [0] * nd, [W] + [0] * (nd - 1)]
+        cases += [vals[i * nd:(i + 1) * nd] for i in range(len(vals) // nd)][:30]
+        yield from cases
+
+
 @pytest.mark.parametrize("p", [65537, 16777213, 2147483647, 68719476731, 1125899906842597,
                                4503599627370449, 2 ** 16, 2 ** 52 - 1])
 def test_short_tile_fold_exact(p):
-    lim = 1024 * 7 * 2 ** 14  # 1024 k-terms of at most 7 digit products of |d| <= 128
-    rng = gen.uniform_mod(p % 1000, 93, 3000, 2 * lim + 1)
-    vals = [int(x) - lim for x in rng]
-    for nd in (5, 7, 9, 11, 13):
-        cases = [[lim] * nd, [-lim] * nd, [lim, -lim] * (nd // 2) + [lim] * (nd % 2),
-                 [-lim, lim] * (nd // 2) + [-lim] * (nd % 2), [0] * nd, [lim] + [0] * (nd - 1)]
-        cases += [vals[i * nd:(i + 1) * nd] for i in range(len(vals) // nd)][:40]
-        for w in cases:
-            want = sum(256 ** s * ws for s, ws in enumerate(w)) % p
-            assert _fold_short(w, p) == want
+    # persistent tiles: K <= 1024 k-terms of at most 7 digit products, p >= 2^16
+    W = 1024 * 7 * 2 ** 14
+    for w in _direct_cases(p, W, 93):
+        assert _fold_direct(w, p, 65793 * W) == sum(256 ** s * ws for s, ws in enumerate(w)) % p
+
+
+@pytest.mark.parametrize("K,D", [(128, 8), (2048, 8), (16320, 8), (64, 1), (1024, 4)])
+def test_crt_direct_fold_exact(K, D):
+    # the CRT launcher takes fold_direct when 65793 K D 2^14 <= (2^27 - 2) p
+    # for every modulus; checked at the smallest such p and above
+    W = K * D * 2 ** 14
+    gmax = 65793 * W
+    pmin = max(5, -(-gmax // (2 ** 27 - 2)))
+    for p in (pmin, pmin + 1, 2 * pmin + 7, 2 ** 31 - 1, 2 ** 52 - 1):
+        if p < pmin or p >= 2 ** 52:
+            continue
+        for w in _direct_cases(p, W, 94):
+            assert _fold_direct(w, p, gmax) == sum(256 ** s * ws for s, ws in enumerate(w)) % p
 
 
 @pytest.mark.parametrize("shape", [(512, 512, 131072), (16384, 16384, 256), (4096, 4096, 4096), (64, 64, 1 << 20),
