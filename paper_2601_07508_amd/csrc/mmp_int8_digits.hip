@@ -121,6 +121,7 @@ int launch_gemm(const Int8Args* jobs, int njobs, hipStream_t s) {
   timer_commit(t, e);
   return e;
 }
+
 // Workgroups of the persistent kernel the current device holds at once:
 // compute units x resident workgroups per unit (registers and LDS decide;
 // cached per device).
