@@ -47,7 +47,7 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
   // copies as digit_tile_loop's, written out again here: routing both
   // through one shared helper changed the code the compiler generates for
   // the main digit GEMM (a longer loop), which this form must not touch.
-  uint64_t voff[IPW];
+  uint32_t voff[IPW];  // planes below 4 GB (launcher)
   auto set_offsets = [&](int64_t m0, int64_t n0) {
 #pragma unroll
     for (int e = 0; e < IPW; e++) {
@@ -56,10 +56,10 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
         voff[e] = 0;  // no copy
       } else if (t < D * BM / 16) {
         const int64_t row = m0 + 16 * (t % (BM / 16)) + rl;
-        voff[e] = (uint64_t)plane_at(row < a.m ? row : a.m - 1, 16 * ql, a.kp);
+        voff[e] = (uint32_t)plane_at(row < a.m ? row : a.m - 1, 16 * ql, a.kp);
       } else {
         const int64_t row = n0 + 16 * ((t - D * BM / 16) % (BN / 16)) + rl;
-        voff[e] = (uint64_t)plane_at(row < a.n ? row : a.n - 1, 16 * ql, a.kp);
+        voff[e] = (uint32_t)plane_at(row < a.n ? row : a.n - 1, 16 * ql, a.kp);
       }
     }
   };

@@ -146,35 +146,29 @@ int64_t persistent_slots() {
 }
 
 // One product of 64 x 64 tiles whose tiles are short (at most
-// kPersistentMaxStages k-stages, whole k per tile, within one int32 block)
-// and at least twice as many as the device holds workgroups: the persistent
-// kernel, one workgroup per resident slot.
+// kPersistentMaxStages k-stages, whole k per tile, within one int32 block),
+// at least twice as many as the device holds workgroups, and planes below
+// 4 GB (the kernel keeps 32-bit copy offsets): the persistent kernel, one
+// workgroup per resident slot.
 constexpr int64_t kPersistentMaxStages = 16;
-// Not at 5 digits: there the persistent kernel's extra loop state does not
-// fit the 256 VGPRs of two waves per SIMD without spilling.
 int launch_persistent_if_short(const Int8Args& g, hipStream_t s, bool* launched) {
   using namespace i8d;
   constexpr int D = MMP_D;
   using S = I8Shape<D, false>;
   *launched = false;
-  if constexpr (D == 5) {
-    (void)g;
-    (void)s;
-    return 0;
-  } else {
-    if (g.splits > 1 || g.kp <= 0 || g.kp / kBK8 > kPersistentMaxStages || g.kp > g.kblock) return 0;
-    const int64_t tiles = ((g.m + S::BM - 1) / S::BM) * ((g.n + S::BN - 1) / S::BN);
-    const int64_t slots = persistent_slots<D>();
-    if (tiles < 2 * slots || tiles > 0x7fffffff) return 0;
-    const GemmArgs a = gemm_args(g);
-    *launched = true;
-    TimerTok* t = timer_begin("int8_gemm_persistent");
-    hipExtLaunchKernelGGL((int8_digits_gemm_persistent_kernel<D>), dim3((unsigned)slots), dim3(S::THREADS), 0, s,
-                          timer_start(t), timer_stop(t), 0, a);
-    const int e = (int)hipGetLastError();
-    timer_commit(t, e);
-    return e;
-  }
+  if (g.splits > 1 || g.kp <= 0 || g.kp / kBK8 > kPersistentMaxStages || g.kp > g.kblock) return 0;
+  if (digit_planes_bytes(1, std::max(g.m, g.n), g.kp) >= ((size_t)1 << 32)) return 0;
+  const int64_t tiles = ((g.m + S::BM - 1) / S::BM) * ((g.n + S::BN - 1) / S::BN);
+  const int64_t slots = persistent_slots<D>();
+  if (tiles < 2 * slots || tiles > 0x7fffffff) return 0;
+  const GemmArgs a = gemm_args(g);
+  *launched = true;
+  TimerTok* t = timer_begin("int8_gemm_persistent");
+  hipExtLaunchKernelGGL((int8_digits_gemm_persistent_kernel<D>), dim3((unsigned)slots), dim3(S::THREADS), 0, s,
+                        timer_start(t), timer_stop(t), 0, a);
+  const int e = (int)hipGetLastError();
+  timer_commit(t, e);
+  return e;
 }
 }  // namespace
 
