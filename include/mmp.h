@@ -399,10 +399,11 @@ int mmp_last_hip_error(void);
 
 /* Per-phase kernel time.  When enabled, every launch the library makes is
  * bracketed by a HIP event pair on its stream; mmp_timers_read waits for the
- * recorded events and reports, per phase ("fp64_words", "int8_digitize_a",
- * "int8_digitize_b", "int8_gemm", "int8_gemm_persistent", ...), the number
- * of launches and their summed device time.  This measures the paper's time breakdown (Section
- * 4.2.1) on the device instead of on the host. */
+ * recorded events and reports, per phase ("fp64_words", "int8_digitize" for
+ * both operands in one launch, "int8_digitize_a" or "int8_digitize_b" for
+ * one, "int8_gemm", "int8_gemm_persistent", ...), the number of launches and
+ * their summed device time.  This measures the paper's time breakdown
+ * (Section 4.2.1) on the device instead of on the host. */
 typedef struct {
   char name[32];
   int64_t launches;

@@ -76,13 +76,14 @@ struct IntegerIn {
 // a row) and stores one 8-byte word per plane.  VEC: the row's entries are
 // 16-byte aligned (aligned base, even ld), so whole groups of 8 load as four
 // 16-byte vectors.
+// One workgroup's part: column chunk bx, row groups by, by + gy, ...
 template <int D, class In, bool VEC>
-__global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, int64_t cols, int64_t ld,
-                                                            int64_t kp, int8_t* __restrict__ out) {
-  const int64_t c0 = (int64_t)blockIdx.x * 128 + (threadIdx.x & 15) * 8;
+__device__ __forceinline__ void digitize_rows_part(const In& X, int64_t rows, int64_t cols, int64_t ld, int64_t kp,
+                                                   int8_t* __restrict__ out, int64_t bx, int64_t by, int64_t gy) {
+  const int64_t c0 = bx * 128 + (threadIdx.x & 15) * 8;
   if (c0 >= kp) return;
   const int64_t plane = plane_size(rows, kp);
-  for (int64_t r = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4); r < rows; r += (int64_t)gridDim.y * 16) {
+  for (int64_t r = by * 16 + (threadIdx.x >> 4); r < rows; r += gy * 16) {
     int64_t v[8];
     if (VEC && c0 + 8 <= cols) {
       X.load8(r * ld + c0, v);
@@ -105,16 +106,23 @@ __global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, 
   }
 }
 
+template <int D, class In, bool VEC>
+__global__ __launch_bounds__(256) void digitize_rows_kernel(In X, int64_t rows, int64_t cols, int64_t ld,
+                                                            int64_t kp, int8_t* __restrict__ out) {
+  digitize_rows_part<D, In, VEC>(X, rows, cols, ld, kp, out, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
 // B (krows x ncols, row-major, ld) -> D transposed planes of ncols x kp.
 // 64 x 64 tiles through LDS so that both the reads (along n) and the writes
 // (16 columns' 64 k-bytes, one whole block, per 256 threads) are contiguous.
+// One workgroup's part: 64 x 64 tile number `t` (n fastest), through `tile`.
 template <int D, class In>
-__global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows, int64_t ncols, int64_t ld,
-                                                            int64_t kp, int8_t* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) uint8_t tile[D][64][64 + 4];
+__device__ __forceinline__ void digitize_cols_part(const In& X, int64_t krows, int64_t ncols, int64_t ld, int64_t kp,
+                                                   int8_t* __restrict__ out, int64_t t,
+                                                   uint8_t (&tile)[D][64][64 + 4]) {
   const int64_t tiles_n = (ncols + 63) / 64;
-  const int64_t k0 = (int64_t)(blockIdx.x / tiles_n) * 64;
-  const int64_t n0 = (int64_t)(blockIdx.x % tiles_n) * 64;
+  const int64_t k0 = (t / tiles_n) * 64;
+  const int64_t n0 = (t % tiles_n) * 64;
   const int tid = threadIdx.x;
   // read: 64 k-rows x 64 columns; thread tid takes column tid % 64 of k-rows
   // tid / 64 + 4 u, u < 16, all 16 loads issued before any is used
@@ -146,6 +154,30 @@ __global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows,
     if (ocol < ncols && kq < kp)  // 4 digit bytes, k-order, read as one word (rows are 68 bytes)
       *(uint32_t*)(out + i * plane + plane_at(ocol, kq, kp)) = *(const uint32_t*)&tile[i][cn][4 * w];
   }
+}
+
+template <int D, class In>
+__global__ __launch_bounds__(256) void digitize_cols_kernel(In X, int64_t krows, int64_t ncols, int64_t ld,
+                                                            int64_t kp, int8_t* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint8_t tile[D][64][64 + 4];
+  digitize_cols_part<D, In>(X, krows, ncols, ld, kp, out, blockIdx.x, tile);
+}
+
+// A's rows and B's columns of one product in a single launch: workgroups
+// below gx * gy take the row part (column chunk b % gx, row groups b / gx +
+// gy i), the rest the 64 x 64 column tiles.  One kernel boundary fewer, and
+// the two passes' tails overlap.
+template <int D, class In, bool VEC>
+__global__ __launch_bounds__(256) void digitize_pair_kernel(In XA, int64_t m, int64_t k, int64_t lda, In XB,
+                                                            int64_t n, int64_t ldb, int64_t kp,
+                                                            int8_t* __restrict__ outA, int8_t* __restrict__ outB,
+                                                            int64_t gx, int64_t gy) {
+  __shared__ __attribute__((aligned(16))) uint8_t tile[D][64][64 + 4];
+  const int64_t b = blockIdx.x, nrows = gx * gy;
+  if (b < nrows)  // uniform per workgroup: the row part has no barrier
+    digitize_rows_part<D, In, VEC>(XA, m, k, lda, kp, outA, b % gx, b / gx, gy);
+  else
+    digitize_cols_part<D, In>(XB, k, n, ldb, kp, outB, b - nrows, tile);
 }
 
 }  // namespace i8d

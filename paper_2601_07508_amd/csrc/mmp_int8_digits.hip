@@ -65,10 +65,33 @@ int MMP_CAT(launch_int8_digitize_side_, MMP_D)(int side, const double* X, int64_
 }
 
 int MMP_CAT(launch_int8_digitize_, MMP_D)(const Int8Args& g, void* stream) {
+  using namespace i8d;
   constexpr int D = MMP_D;
   // planes made here: A's (unless resident), then B's (unless resident)
   int8_t* Ad = g.work;
   int8_t* Bd = g.work + (g.resident_a ? (size_t)0 : digit_planes_bytes(D, g.m, g.kp));
+  if (!g.resident_a && !g.resident_b && g.m > 0 && g.n > 0 && g.kp > 0) {
+    // both operands: one launch (A's row part, then B's column tiles)
+    int64_t top = 0;
+    for (int i = 0; i < D; i++) top = top * 256 + 127;
+    const ResidueIn ia{g.A, (int64_t)g.p, top}, ib{g.B, (int64_t)g.p, top};
+    const int64_t gx = (g.kp + 127) / 128, gy = std::min<int64_t>((g.m + 15) / 16, 65535);
+    const int64_t total = gx * gy + (g.kp / 64) * ((g.n + 63) / 64);
+    if (total > 0x7fffffff) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    TimerTok* t = timer_begin("int8_digitize");
+    if (((uintptr_t)g.A % 16) == 0 && g.lda % 2 == 0)
+      hipExtLaunchKernelGGL((digitize_pair_kernel<D, ResidueIn, true>), dim3((unsigned)total), dim3(256), 0, s,
+                            timer_start(t), timer_stop(t), 0, ia, g.m, g.k, g.lda, ib, g.n, g.ldb, g.kp, Ad, Bd, gx,
+                            gy);
+    else
+      hipExtLaunchKernelGGL((digitize_pair_kernel<D, ResidueIn, false>), dim3((unsigned)total), dim3(256), 0, s,
+                            timer_start(t), timer_stop(t), 0, ia, g.m, g.k, g.lda, ib, g.n, g.ldb, g.kp, Ad, Bd, gx,
+                            gy);
+    const hipError_t e = hipGetLastError();
+    timer_commit(t, (int)e);
+    return (int)e;
+  }
   if (!g.resident_a)
     if (int e = MMP_CAT(launch_int8_digitize_side_, MMP_D)(0, g.A, g.m, g.k, g.lda, g.kp, g.p, Ad, stream)) return e;
   if (!g.resident_b)

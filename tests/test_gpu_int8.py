@@ -231,6 +231,7 @@ def test_int8_many_short_tiles(p):
         mmp.timers_enable(False)
         assert t.get("int8_gemm_persistent", (0, 0))[0] == 1, t
         assert t.get("int8_gemm", (0, 0))[0] == 0, t
+        assert t.get("int8_digitize", (0, 0))[0] == 1, t  # both operands, one launch
         assert_exact(C[rows], oracle.mm_modp(p, A[rows], B))
 
 

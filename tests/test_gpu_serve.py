@@ -141,6 +141,7 @@ def test_resident_operand_switches_auto_to_int8_form():
         t = mmp.timers_read(reset=True)
     say("timers", t)
     assert t.get("int8_gemm", (0, 0))[0] == 1 and t.get("int8_digitize_a", (0, 0))[0] == 0
+    assert t.get("int8_digitize", (0, 0))[0] == 0 and t.get("int8_digitize_b", (0, 0))[0] == 1
     assert "fp64_words" not in t or t["fp64_words"][0] == 0
     want = oracle.mm_modp(p, A, B).astype(np.float64)
     assert np.array_equal(C.cpu().numpy(), want)
