@@ -138,6 +138,16 @@ def test_int8_strided_and_stream():
     out = Cb.cpu().numpy()
     assert_exact(out[:, :n], oracle.mm_modp(p, A, B))
     assert np.all(out[:, n:] == 7.0)
+    # A's rows starting 8 bytes past a 16-byte boundary, even row stride:
+    # the digitizing reads A's entries one by one
+    Ae = torch.zeros((m, k + 4), dtype=torch.float64, device="cuda")
+    Ae[:, 1:k + 1] = dev(A)
+    C2 = torch.full((m, n), -1.0, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    assert Ae[:, 1:].data_ptr() % 16 == 8 and Ae.stride(0) % 2 == 0
+    mmp.mm_modp_async(Ae[:, 1:k + 1], Bb[:, :n], C2, p, form=INT8)
+    torch.cuda.synchronize()
+    assert_exact(C2.cpu().numpy(), oracle.mm_modp(p, A, B))
 
 
 @pytest.mark.parametrize("p", [8388593, 68719476731, 1125899906842597, 4503599627370449])
