@@ -7,8 +7,12 @@ cores with in-loop modular reductions, recombination and the single store
 of C (the whole method of Section 3.2).  Effective GFLOP/s is 2 m n k / t
 (the paper's metric, Section 4.1).
 
-Default workload: square m = n = k = 4096 with p the largest prime below
-2^36 and the planner's (u, v); other workloads by --config/--variant.
+Default workload: square m = n = k = 8192 with p the largest prime below
+2^50, (u, v) = (2, 2) binary64 words on the FP64 matrix cores under the
+paper's block bound (Prop. UVMW, eq. cAcB: lambda = 7); beside it the same
+product under the other forms and bounds, its all-(p-1) worst case, the
+4096^3 workloads at 36 and 26 bits, a served stream of mixed products and
+the oracle on the host.  Other workloads by --config/--variant.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -83,6 +87,7 @@ def cpu_baseline(prob, A, B, budget_s=12.0):
         "value": 2.0 * rows * prob.n * prob.k / t / 1e9,
         "unit": "GFLOP/s",
         "cores": oracle.threads(),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": f"rows 0..{rows - 1} of the {prob.m}x{prob.n}x{prob.k} product "
                   f"({rows * prob.n} outputs, {t:.1f} s, 128-bit integer dot products)",
@@ -353,18 +358,116 @@ def sweep_bits(args, mmp, torch, gen):
             sys.exit(1)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _leg(mmp, torch, dA, dB, p, u, v, steps, ref=None, **kw):
+    """Times one form/bound of a product on resident inputs; returns its record
+    and output.  Kernel time comes from the library's launch events."""
+    m, k = dA.shape
+    n = dB.shape[1]
+    C = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    pl = mmp.plan(p, m, n, k, u, v, **kw)
+    stream = torch.cuda.current_stream()
+    ms = _time(torch, lambda: mmp.mm_modp_async(dA, dB, C, p, u, v, stream=stream, **kw), 2, steps)
+    mmp.timers_read(reset=True)
+    mmp.timers_enable(True)
+    for _ in range(steps):
+        mmp.mm_modp_async(dA, dB, C, p, u, v, stream=stream, **kw)
+    torch.cuda.synchronize()
+    mmp.timers_enable(False)
+    phases = mmp.timers_read(reset=True)
+    mnk = float(m) * n * k
+    if pl["form"] == 1:
+        phase, peak, work = "fp64_words", FP64_MFMA_PEAK_TFLOPS, 2.0 * pl["u"] * pl["v"] * mnk
+        desc = {"form": "fp64_words", "dtype": "f64", "uv": [pl["u"], pl["v"]], "lambda": pl["lambda"],
+                "kblock": pl["kblock"], "slots": pl["slots"], "biased_reduction": bool(pl["biased"]),
+                "extended_block": bool(pl["extended"]), "centered_words": bool(pl["centered"])}
+    else:
+        phase = "int8_gemm_persistent" if "int8_gemm_persistent" in phases else "int8_gemm"
+        peak, work = INT8_MFMA_PEAK_TOPS, 2.0 * pl["digits_a"] * pl["digits_b"] * mnk
+        desc = {"form": "int8_digits", "dtype": "int8 digits, int32 accumulation, f64 fold",
+                "digits": pl["digits_a"]}
+    launches, tot = phases.get(phase, (0, 0.0))
+    kms = tot / max(launches, 1)
+    rec = dict(desc)
+    rec.update({"ms": round(ms, 4), "eff_gflops": round(2.0 * mnk / (ms * 1e-3) / 1e9, 1),
+                "kernel_ms": round(kms, 4),
+                "kernel_frac_of_peak": round(work / (kms * 1e-3) / 1e12 / peak, 4) if kms > 0 else None})
+    if ref is not None:
+        rec["identical_to_headline"] = bool(torch.equal(C, ref))
+    return rec, C
+
+
+def extra_legs(args, mmp, torch, gen, prob, dA, dB, dC):
+    """The headline product under the other forms and bounds, its all-(p-1)
+    worst case, and the 4096^3 workloads at 36 and 26 bits."""
+    steps = max(3, min(args.steps, 10))
+    out = {}
+    p = prob.p
+    forms = {}
+    for name, u, v, kw in (("fp64_words_lambda4", prob.u, prob.v, {"force_kblock": 4}),
+                           ("fp64_words_extended_bound", prob.u, prob.v, {"extended_block": True}),
+                           ("fp64_words_centered_words", prob.u, prob.v, {"centered_words": True}),
+                           ("int8_digits", 0, 0, {"form": 2})):
+        log("leg", name)
+        forms[name], _ = _leg(mmp, torch, dA, dB, p, u, v, steps, ref=dC, **kw)
+    out["same_workload_other_forms"] = forms
+    # all entries p - 1: every word at its maximum; C = k mod p since (p-1)^2 = 1 mod p
+    log("leg worst case")
+    full = torch.full_like(dA, float(p - 1))
+    want = float(prob.k % p)
+    wc = {}
+    for name, u, v, kw in (("fp64_words", prob.u, prob.v, {}), ("int8_digits", 0, 0, {"form": 2})):
+        rec, C = _leg(mmp, torch, full, full, p, u, v, steps, **kw)
+        rec["all_equal_k_mod_p"] = bool(torch.all(C == want))
+        wc[name] = rec
+    out["all_p_minus_1"] = wc
+    del full
+    # square 4096^3: 36 bits (the planner's choice, and the FP64 words it
+    # would take), and 26 bits with the single word forced (lambda = 2)
+    for tag, legs in ((0, (("auto", 0, 0, {}), ("fp64_words", 0, 0, {"form": 1}))),
+                      (1, (("forced_uv11", 1, 1, {}), ("fp64_words", 0, 0, {"form": 1}),
+                           ("int8_digits", 0, 0, {"form": 2})))):
+        pr = gen.config_problems(2)[tag]
+        log("workload", pr.tag)
+        a = torch.from_numpy(pr.a().astype("float64")).cuda()
+        b = torch.from_numpy(pr.b().astype("float64")).cuda()
+        recs, ref = {}, None
+        for name, u, v, kw in legs:
+            rec, C = _leg(mmp, torch, a, b, pr.p, u, v, steps, ref=ref, **kw)
+            if ref is None:
+                ref = C
+            else:
+                rec["identical_to_first"] = rec.pop("identical_to_headline")
+            recs[name] = rec
+        out[pr.tag] = {"p": pr.p, "shape": [pr.m, pr.n, pr.k], "legs": recs}
+        del a, b, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", type=int, default=2, help="workload group 1..4")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3, help="workload group 1..4")
     ap.add_argument("--variant", type=int, default=0, help="index inside the workload group")
     ap.add_argument("--form", type=int, default=0, help="0 auto, 1 FP64 words, 2 INT8 digits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", type=int, default=200,
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other forms, the worst case and the 4096^3 legs of the default run")
+    ap.add_argument("--serve", type=int, default=2000,
                     help="requests in the serving measurement (0: skip it)")
-    ap.add_argument("--serve-loads", default="0.8",
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="comma-separated fractions of the measured capacity to offer")
     ap.add_argument("--crt", action="store_true",
                     help="time the multi-modular job (2048^3 integers < 2^60 against 32 primes) instead")
@@ -376,6 +479,8 @@ def main():
                     help="comma list of bitsizes: the unbalanced 10923x32768x32 workload, all forms")
     ap.add_argument("--centered", action="store_true",
                     help="FP64 form: centered words and their block bound")
+    ap.add_argument("--force-kblock", type=int, default=0,
+                    help="FP64 form: k-terms per block (0: the planner's)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the product, time a plain device copy of this many bytes "
                          "(the reference kernel for scaling HBM counters)")
@@ -419,8 +524,9 @@ def main():
     prob = gen.config_problems(args.config)[args.variant]
     if args.form == 2:  # the INT8-digit form takes no word counts
         prob.u = prob.v = 0
-    plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, form=args.form, extended_block=args.extended,
-                    centered_words=args.centered)
+    kw = dict(form=args.form, extended_block=args.extended, centered_words=args.centered,
+              force_kblock=args.force_kblock)
+    plan = mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v, **kw)
     log("workload", prob.tag, "plan", plan)
 
     A = prob.a()
@@ -431,8 +537,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        mmp.mm_modp_async(dA, dB, dC, prob.p, prob.u, prob.v, stream=stream, form=args.form,
-                          extended_block=args.extended, centered_words=args.centered)
+        mmp.mm_modp_async(dA, dB, dC, prob.p, prob.u, prob.v, stream=stream, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -476,11 +581,18 @@ def main():
     if plan["form"] == 1:
         kernel, phase, peak, unit = "fp64_words_kernel", "fp64_words", FP64_MFMA_PEAK_TFLOPS, "TFLOP/s"
         work = 2.0 * plan["u"] * plan["v"] * mnk  # word flops per launch
+        dtype = "f64"
+        form_desc = (f"(u,v) = ({plan['u']},{plan['v']}) binary64 words on FP64 MFMA, k-block "
+                     f"{plan['kblock']} of the bound {plan['lambda']}"
+                     + (" (extended bound)" if plan["extended"] else
+                        " (centered words)" if plan["centered"] else " (the paper's lambda)"))
     else:
         kernel, phase, peak, unit = "int8_digits_gemm_kernel", "int8_gemm", INT8_MFMA_PEAK_TOPS, "TOP/s"
         if "int8_gemm_persistent" in phases:  # many short tiles: the persistent form of the digit GEMM
             kernel, phase = "int8_digits_gemm_persistent_kernel", "int8_gemm_persistent"
         work = 2.0 * plan["digits_a"] * plan["digits_b"] * mnk  # digit-product int8 ops per launch
+        dtype = "int8 digits, int32 accumulation, f64 fold"
+        form_desc = f"{plan['digits_a']} signed 8-bit digits per entry on INT8 MFMA"
     launches, total_ms = phases.get(phase, (0, 0.0))
     kern_ms = total_ms / max(launches, 1)
     achieved = work / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
@@ -495,6 +607,8 @@ def main():
         "kernel_ms": round(kern_ms, 4),
         "algorithmic_work_per_launch": work,
     }
+    shape = "square" if prob.m == prob.n == prob.k else "product"
+    fill = ", all entries p - 1" if prob.fill == "pmax" else ""
     out = {
         "metric": "effective 2mnk GFLOP/s of C=AB mod p",
         "value": round(eff, 2),
@@ -506,13 +620,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic: seeded uniform integers in [0, p) stored as binary64",
+        "dtype": dtype,
+        "data": "synthetic: seeded uniform integers in [0, p) stored as binary64" if not fill else
+                "synthetic: every entry p - 1 (worst case) stored as binary64",
         "config": {
-            "workload": f"square {prob.m}x{prob.n}x{prob.k}, p = {prob.p} (largest prime below "
-                        f"2^{prob.p.bit_length()}), exact C = AB mod p",
+            "workload": f"{shape} {prob.m}x{prob.n}x{prob.k}, p = {prob.p} (largest prime below "
+                        f"2^{prob.p.bit_length()}){fill}, {form_desc}, exact C = AB mod p",
             "m": prob.m, "n": prob.n, "k": prob.k, "p": prob.p, "bits": prob.p.bit_length(),
             "u": plan["u"], "v": plan["v"], "lambda": plan["lambda"], "kblock": plan["kblock"],
+            "slots": plan["slots"], "biased_reduction": bool(plan["biased"]),
             "digits": plan["digits_a"], "extended_block": bool(plan["extended"]),
             "centered_words": bool(plan["centered"]),
             "form": "fp64_words" if plan["form"] == 1 else "int8_digits", "tile": plan["tile"],
@@ -521,9 +637,15 @@ def main():
         "phases_ms_per_step": {k: round(v[1] / max(args.steps, 1), 4) for k, v in phases.items()},
         "source_digest": digest,
     }
+    default_run = (args.config == 3 and args.variant == 0 and args.form == 0 and not args.extended
+                   and not args.centered and not args.force_kblock)
+    if default_run and not args.no_extras:
+        log("extra legs ...")
+        out["extras"] = extra_legs(args, mmp, torch, gen, prob, dA, dB, dC)
     if args.serve > 0:
         log("serving ...")
         del dA, dB, dC
+        torch.cuda.empty_cache()
         out["serving"] = serving(mmp, torch, gen, args.serve, [float(x) for x in args.serve_loads.split(",")])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -152,8 +152,8 @@ typedef struct {
                              4, 8 or 16 with the excess slots holding zeros,
                              or equal to kblock, a multiple of 4) */
   int lazy;               /* 1: in-loop reductions omit Alg. 1's corrections
-                             (result in [-p, 2p), or [-2^t, -2^t + 4p) with
-                             extended); the final one is complete */
+                             (result in [-p, 2p), or [-2^t, -2^t + 4p) when
+                             biased); the final one is complete */
   int extended;           /* 1: the extended block bound (mmp_opts) is used */
   int tile;               /* kernel tile id */
   int bm, bn, bk;         /* workgroup tile (rows, cols, k-slots per stage) */
@@ -165,6 +165,15 @@ typedef struct {
   size_t workspace_bytes; /* device workspace the call needs */
   int centered;           /* 1: centered words and the round-to-nearest
                              in-loop reduction (mmp_opts.centered_words) */
+  int biased;             /* 1: the correction-free in-loop reduction is the
+                             biased one, c = floor(x q + K) with
+                             K = floor(2^t / p) - 1, which leaves the
+                             accumulator in [-2^t, -2^t + 4p): always with
+                             extended, and under the paper's bound when a
+                             block of kblock <= lambda terms started in
+                             [-p, 2p) could pass 2^t but one started there
+                             cannot (e.g. (2,2) at 50 bits: kblock =
+                             lambda = 7) */
 } mmp_plan_t;
 
 /* One product of a batch. */

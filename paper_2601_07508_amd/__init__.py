@@ -51,7 +51,7 @@ class MmpPlan(ctypes.Structure):
                 ("tile", _int),
                 ("bm", _int), ("bn", _int), ("bk", _int), ("digits_a", _int), ("digits_b", _int),
                 ("kblock_int8", _i64), ("q", _dbl), ("est_seconds", _dbl), ("splits", _int),
-                ("workspace_bytes", _sz), ("centered", _int)]
+                ("workspace_bytes", _sz), ("centered", _int), ("biased", _int)]
 
     def as_dict(self):
         d = {f[0]: getattr(self, f[0]) for f in self._fields_}

@@ -41,6 +41,9 @@ __device__ __forceinline__ int bswz(int slot, int c) { return c ^ ((slot & 1) <<
 // Raw buffer loads (dword 3 of the resource for the gfx9 family): reads at or
 // past the resource's byte count return zero instead of touching memory.
 constexpr int kBufferWord3 = 0x00020000;
+// A byte offset past every resource the kernel builds (their byte counts are
+// clamped to 2^31 - 1): a load from it returns zero.
+constexpr uint32_t kIdleOffset = 0xFFFFFFF0u;
 __device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   typedef int v2i __attribute__((ext_vector_type(2)));
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
@@ -207,8 +210,10 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
   //     so its LDS destinations are affine in e;
   //   padded stages (PAD, KR < 16 real terms in 16 slots): real term kk goes
   //     to slot (kk / L) S + kk % L and the other slots keep their zeros;
-  //     elements past the slab are idle: zero values written to A's pad
-  //     column (never read) and to B's slot L (a zero slot when L < S).
+  //     elements past the slab are idle: their byte offset lies past every
+  //     resource (at most 2^31 - 1 bytes), so they load zero, which they
+  //     write to A's pad column (never read) and to B's slot L (a zero slot
+  //     when L < S).
   const int KR = a.KR;
   constexpr int AROWS = kThreads / kBK;  // A rows between a thread's elements
   constexpr int BROWS = kThreads / BN;   // B k-rows between a thread's elements
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
       const bool valid = idx < BM * KR;
       const int r = valid ? idx / KR : 0, kk = valid ? idx % KR : 0;
       const int slot = (kk / a.L) * a.S + kk % a.L;
-      a_off[e] = (uint32_t)(((int64_t)r * a.lda + kk) * 8);
+      a_off[e] = valid ? (uint32_t)(((int64_t)r * a.lda + kk) * 8) : kIdleOffset;
       a_meta[e] = valid ? (r * LDA + slot) | (kk << 16) : kBK | (kBK << 16);
     }
 #pragma unroll
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
       const bool valid = idx < KR * BN;
       const int kk = valid ? idx / BN : 0, c = valid ? idx % BN : 0;
       const int slot = (kk / a.L) * a.S + kk % a.L;
-      b_off[e] = (uint32_t)(((int64_t)kk * a.ldb + c) * 8);
+      b_off[e] = valid ? (uint32_t)(((int64_t)kk * a.ldb + c) * 8) : kIdleOffset;
       b_meta[e] = valid ? (slot * LDB + bswz(slot, c)) | (kk << 16) : (a.L * LDB + bswz(a.L, 0)) | (kBK << 16);
     }
   }
@@ -267,12 +272,12 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
 #pragma unroll
         for (int e = 0; e < NA; e++) ra[e] = ok ? ra[e] : 0.0;
       }
-    } else {
-      const int lim = (int)(left < KR ? left : KR);
+    } else if (left < KR) {
+      // the k tail: A's terms past k hold other data; B's k-rows past k lie
+      // beyond its resource and already read as zero
+      const int lim = (int)left;
 #pragma unroll
       for (int e = 0; e < NA; e++) ra[e] = (a_meta[e] >> 16) < lim ? ra[e] : 0.0;
-#pragma unroll
-      for (int e = 0; e < NB; e++) rb[e] = (b_meta[e] >> 16) < lim ? rb[e] : 0.0;
     }
   };
   auto store_stage_as = [&](int buf, auto centered) {

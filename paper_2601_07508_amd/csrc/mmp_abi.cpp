@@ -184,7 +184,7 @@ Fp64Args make_fp64_args(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k, c
   a.ksteps_per_block = pl.slots / 4;
   a.lazy = pl.lazy;
   a.splits = 1;
-  if (pl.extended) {
+  if (pl.biased) {  // biased reduction: the extended bound, or a paper block that needs the signed range
     const uint64_t K = (kTwoT / pl.p) - 1;  // K p <= 2^t - p
     a.bias = (double)K;
     a.acc_init = -(double)(K * pl.p);

@@ -141,25 +141,44 @@ struct KBlock {
   bool lazy;
   bool extended;
   double cost;
+  bool biased;  // the in-loop reduction is the biased one (range [-2^t, -2^t + 4p))
 };
 
-// Best (L, S) for one word pair.  Paper mode: L <= the paper's lambda, the
-// correction-free reduction where lazy_block_ok allows it.  With extended
+// Correction-free reduction for a block of L terms within the paper's
+// bound: the plain form when a block started in [-p, 2p) stays within 2^t,
+// else the biased form when a block started in [-2^t, -2^t + 4p) stays
+// within [-2^t, 2^t].  The block length is the paper's either way; only the
+// range the accumulator restarts from differs.  Returns false (full Alg. 1
+// in the loop) when neither holds or strict reductions are asked for.
+bool correction_free(uint64_t p, int u, int v, int64_t L, bool strict, bool* biased) {
+  *biased = false;
+  if (strict) return false;
+  if (lazy_block_ok(p, u, v, L)) return true;
+  if (extended_block_ok(p, u, v, L)) {
+    *biased = true;
+    return true;
+  }
+  return false;
+}
+
+// Best (L, S) for one word pair.  Paper mode: L <= the paper's lambda, a
+// correction-free reduction where correction_free allows one.  With extended
 // allowed, blocks under the extended bound compete too (biased reduction);
 // near p = 2^(t-1) that bound is the smaller one and the paper mode wins.
 // Centered words: L <= centered_lambda, always the one-step reduction.
 KBlock choose_kblock(uint64_t p, int u, int v, int64_t k, bool strict, bool allow_extended,
                      bool centered = false) {
-  KBlock best{0, 0, false, false, 1e300};
+  KBlock best{0, 0, false, false, 1e300, false};
   const int64_t lam_paper = centered ? centered_lambda(p, u, v) : paper_lambda(p, u, v);
   const int64_t lam_ext = allow_extended ? extended_lambda(p, u, v) : 0;
   auto consider = [&](int S, int64_t L, bool ext) {
     if (L < 1 || L > (ext ? lam_ext : lam_paper)) return;
-    const bool lazy = centered || ext || (!strict && lazy_block_ok(p, u, v, L));
+    bool biased = ext;
+    const bool lazy = centered || ext || correction_free(p, u, v, L, strict, &biased);
     double c = block_cost(S, L, lazy);
     // a block longer than k never reduces in the loop: cost of the MFMAs only
     if (L >= k && k > 0) c = 64.0 * (S / 4) / (double)L;
-    if (c < best.cost - 1e-12) best = {L, S, lazy, ext, c};
+    if (c < best.cost - 1e-12) best = {L, S, lazy, ext, c, biased};
   };
   for (int e = 0; e < (allow_extended ? 2 : 1); e++) {
     const bool ext = e == 1;
@@ -444,8 +463,9 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     else if (L % 4 == 0) S = (int)L;
     else return MMP_EINVAL;  // longer blocks must be whole MFMA k-steps
     if (L > ((int64_t)1 << 26)) return MMP_EINVAL;
-    const bool lazy = centered || ext || (!strict && lazy_block_ok(p, bu, bv, L));
-    bk = {L, S, lazy, ext, block_cost(S, L, lazy)};
+    bool biased = ext;
+    const bool lazy = centered || ext || correction_free(p, bu, bv, L, strict, &biased);
+    bk = {L, S, lazy, ext, block_cost(S, L, lazy), biased && !centered};
   } else if (u != 0) {
     bk = choose_kblock(p, bu, bv, k, strict, extended, centered);
   }
@@ -461,6 +481,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   out->slots = bk.S;
   out->lazy = bk.lazy ? 1 : 0;
   out->extended = bk.extended ? 1 : 0;
+  out->biased = bk.biased && !centered ? 1 : 0;
   out->centered = centered ? 1 : 0;
   const int64_t KR = (bk.S <= kBK && bk.L < bk.S) ? (kBK / bk.S) * bk.L : kBK;  // real k-terms per stage
   out->tile = o.tile ? o.tile : pick_tile(bu, bv, m, n, cdiv(k, KR), bk.S, bk.L);

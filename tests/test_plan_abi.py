@@ -79,6 +79,14 @@ def _tight_lazy_ok(p, u, v, L):
     return L * w + 2 * p - 1 <= TWO_T
 
 
+def _tight_biased_ok(p, u, v, L):
+    """The same for the biased reduction: a block starting in
+    [-2^t, -2^t + 4p) stays within [-2^t, 2^t]."""
+    a, b = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+    w = (p - 1) ** 2 if (u, v) == (1, 1) else (a - 1) * (b - 1)
+    return -TWO_T + 4 * p - 1 + L * w <= TWO_T
+
+
 @pytest.mark.parametrize("p", PRIMES[2:])
 @pytest.mark.parametrize("uv", SUPPORTED)
 @pytest.mark.parametrize("k", [1, 7, 100, 4096, 131072])
@@ -93,7 +101,16 @@ def test_plan_invariants(p, uv, k):
         assert 1 <= L <= lam
         assert S >= L and (S in (4, 8, 16) or (S % 4 == 0 and S == L and S >= 12))
         if pl["lazy"]:
-            assert not strict and _tight_lazy_ok(p, u, v, L)
+            assert not strict
+            if pl["biased"]:  # the signed range, for a block within the paper's lambda
+                a_, b_ = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+                w = (p - 1) ** 2 if (u, v) == (1, 1) else a_ * b_  # the paper's charge
+                assert L * w + 2 * p - 1 > TWO_T  # the plain range would not do
+                assert _tight_biased_ok(p, u, v, L)
+            else:
+                assert _tight_lazy_ok(p, u, v, L)
+        else:
+            assert not pl["biased"]
         assert pl["q"] == 1.0 / p
         assert pl["bk"] == 16 and pl["tile"] in (1, 2, 3)
 
@@ -315,19 +332,23 @@ def _lazy_reduce(x, p):
     return d
 
 
-def _emulate_entry(p, u, v, L, lazy, arow, bcol):
+def _emulate_entry(p, u, v, L, lazy, arow, bcol, biased=False):
     a_, b_ = pa.iroot_ceil(p, u), pa.iroot_ceil(p, v)
+    K = TWO_T // p - 1
     k = len(arow)
     acc = [[0] * v for _ in range(u)]
     peak = 0
     for i in range(u):
         for j in range(v):
-            s = 0
+            s = -K * p if biased else 0
             for l0 in range(0, k, L):
                 for l in range(l0, min(k, l0 + L)):
                     s += _words(arow[l], a_, u)[i] * _words(bcol[l], b_, v)[j]
                     peak = max(peak, abs(s))
-                s = _lazy_reduce(s, p) if lazy else s % p
+                if biased:
+                    s = _biased_reduce(s, p, K)
+                else:
+                    s = _lazy_reduce(s, p) if lazy else s % p
             acc[i][j] = s % p
     c = 0
     for i in reversed(range(u)):
@@ -354,9 +375,31 @@ def test_schedule_emulation_worst_case(p):
             k = 3 * L + 1
             arow = [x] * k
             bcol = [p - 1] * k
-            c, peak = _emulate_entry(p, u, v, L, bool(pl["lazy"]), arow, bcol)
+            c, peak = _emulate_entry(p, u, v, L, bool(pl["lazy"]), arow, bcol, bool(pl["biased"]))
             assert c == (k * x * (p - 1)) % p
             assert peak <= TWO_T
+
+
+def test_paper_block_with_the_signed_range_at_50_bits():
+    # (2,2) at p = 2^50 - 27: the paper's lambda is 7 (eq. cAcB).  A block of
+    # 7 started in [-p, 2p) could pass 2^53 (2p + 7 alpha beta > 2^53), so the
+    # plain correction-free reduction allows only 6; the biased one restarts
+    # at the bottom of the signed range and allows the paper's 7, run as 7 of
+    # 8 slots (two MFMA k-steps per reduction instead of one).
+    p = 1125899906842597
+    a_ = pa.iroot_ceil(p, 2)
+    assert pa.block_size(p, 2, 2) == 7 and a_ == 1 << 25
+    assert 7 * a_ * a_ + 2 * p - 1 > TWO_T
+    pl = mmp.plan(p, 8192, 8192, 8192, 2, 2)
+    assert (pl["kblock"], pl["slots"], pl["lazy"], pl["biased"], pl["extended"]) == (7, 8, 1, 1, 0)
+    assert pl["kblock"] <= pl["lambda"] == 7
+    # the negative control of the emulation: 8 terms from the same start pass 2^53
+    K = TWO_T // p - 1
+    worst = -K * p + 4 * p - 1
+    assert worst + 7 * (a_ - 1) ** 2 <= TWO_T
+    # strict reductions keep the paper's range and never bias
+    st = mmp.plan(p, 8192, 8192, 8192, 2, 2, strict_fmod=True)
+    assert st["biased"] == 0 and st["lazy"] == 0
 
 
 # ------------------------------------------------------------------ extended block bound
@@ -428,7 +471,7 @@ def test_extended_schedule_worst_case(p):
 
 def test_extended_doubles_block_at_50_bits():
     p = 1125899906842597
-    assert mmp.plan(p, 64, 64, 4096, 2, 2)["kblock"] == 4       # paper: lambda = 7, MFMA-aligned 4
+    assert mmp.plan(p, 64, 64, 4096, 2, 2)["kblock"] == 7       # paper: lambda = 7, as 7 of 8 slots
     pl = mmp.plan(p, 64, 64, 4096, 2, 2, extended_block=True)
     assert pl["kblock"] == 12 and pl["lambda"] == 7             # extended: 12 allowed, 3 k-steps
     with pytest.raises(mmp.MmpError):
@@ -611,7 +654,7 @@ def test_centered_quadruples_block_at_50_bits():
     p = 1125899906842597
     pl = mmp.plan(p, 8192, 8192, 8192, 2, 2, centered_words=True)
     assert (pl["kblock"], pl["slots"], pl["centered"]) == (28, 28, 1)  # 29 allowed, 7 k-steps
-    assert mmp.plan(p, 8192, 8192, 8192, 2, 2)["kblock"] == 4
+    assert mmp.plan(p, 8192, 8192, 8192, 2, 2)["kblock"] == 7  # the paper's lambda, 7 of 8 slots
     # centered words reach one bit past the paper's (1,1) limit of 26 bits
     p27 = gen.prev_prime(1 << 27)
     assert pa.block_size(p27, 1, 1) < 1
