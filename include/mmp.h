@@ -393,6 +393,38 @@ int mmp_tune_cache_clear(void);
 int mmp_tune_cache_save(const char *path);
 int mmp_tune_cache_load(const char *path);
 
+/* The exact int32 block of the INT8-digit form (the low-precision words of
+ * Section 6; the block length plays the part of the paper's lambda, Section
+ * 2.2).  The digit GEMM sees each entry as an integer x' in [lo, hi] written
+ * with `digits` signed base-256 digits in [-128, 127]; one k-term adds
+ * sum_{i+j=s} a_i b_j to the int32 accumulator of digit weight 256^s.
+ * term_max and term_min are the exact extremes of that sum over all pairs of
+ * entries (any weight s), reached by the entries witness_max = (a, b) and
+ * witness_min at weights weight_max and weight_min; kblock is the largest
+ * multiple of 64 with kblock * term_max <= 2^31 - 1 and
+ * kblock * (-term_min) <= 2^31, the k-terms the GEMM accumulates between
+ * folds (mmp_plan_t.kblock_int8).  Host-only. */
+typedef struct {
+  int digits;
+  int weight_max, weight_min;
+  int64_t lo, hi;
+  int64_t term_max, term_min;
+  int64_t witness_max[2], witness_min[2];
+  int64_t kblock;
+} mmp_int8_bound_t;
+
+/* Residues mod p (entry_bits = 0): x' = x, or x - p when x exceeds
+ * 127 (256^D - 1) / 255, with D = ceil(bitsize(p) / 8).  Integers of
+ * mm_modp_crt (p = 0, 1 <= entry_bits <= 62): x' = x in [0, 2^entry_bits),
+ * with the fewest digits that hold them.  MMP_EINVAL otherwise. */
+int mmp_int8_bound(uint64_t p, int entry_bits, mmp_int8_bound_t *out);
+
+/* The same for any interval lo <= hi of values that `digits` (1..8) signed
+ * digits hold, [-128 (256^D - 1) / 255, 127 (256^D - 1) / 255] (digits = 8:
+ * within int64).  MMP_EINVAL otherwise. */
+int mmp_int8_interval_bound(int digits, int64_t lo, int64_t hi,
+                            mmp_int8_bound_t *out);
+
 /* Device bytes a job occupies: its operands and result (8 (mk + kn + mn))
  * plus its word copies (FP64 words: 8 (u mk + v kn); INT8 digits:
  * da mk + db kn), per the storage cost of Section 3.3. */

@@ -102,6 +102,24 @@ _lib.mmp_tune_cache_load.argtypes = [ctypes.c_char_p]
 _lib.mmp_tune_cache_load.restype = _int
 
 
+class MmpInt8Bound(ctypes.Structure):
+    _fields_ = [("digits", _int), ("weight_max", _int), ("weight_min", _int), ("lo", _i64), ("hi", _i64),
+                ("term_max", _i64), ("term_min", _i64), ("witness_max", _i64 * 2), ("witness_min", _i64 * 2),
+                ("kblock", _i64)]
+
+    def as_dict(self):
+        d = {f[0]: getattr(self, f[0]) for f in self._fields_}
+        d["witness_max"] = tuple(self.witness_max)
+        d["witness_min"] = tuple(self.witness_min)
+        return d
+
+
+_lib.mmp_int8_bound.argtypes = [_u64, _int, ctypes.POINTER(MmpInt8Bound)]
+_lib.mmp_int8_bound.restype = _int
+_lib.mmp_int8_interval_bound.argtypes = [_int, _i64, _i64, ctypes.POINTER(MmpInt8Bound)]
+_lib.mmp_int8_interval_bound.restype = _int
+
+
 class MmpTimer(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", _i64), ("total_ms", _dbl)]
 
@@ -175,6 +193,21 @@ def plan(p: int, m: int, n: int, k: int, u: int = 0, v: int = 0, **opts) -> dict
     out = MmpPlan()
     o = _opts(**opts)
     _check(_lib.mmp_plan(p, u, v, m, n, k, ctypes.byref(o), ctypes.byref(out)), "mmp_plan")
+    return out.as_dict()
+
+
+def int8_bound(p: int = 0, entry_bits: int = 0) -> dict:
+    """The INT8-digit form's exact int32 block for residues mod p, or for the
+    integers below 2^entry_bits of mm_modp_crt (host only; see mmp_int8_bound)."""
+    out = MmpInt8Bound()
+    _check(_lib.mmp_int8_bound(p, entry_bits, ctypes.byref(out)), "mmp_int8_bound")
+    return out.as_dict()
+
+
+def int8_interval_bound(digits: int, lo: int, hi: int) -> dict:
+    """The same for entries whose digit values lie in [lo, hi] (mmp_int8_interval_bound)."""
+    out = MmpInt8Bound()
+    _check(_lib.mmp_int8_interval_bound(digits, lo, hi, ctypes.byref(out)), "mmp_int8_interval_bound")
     return out.as_dict()
 
 

@@ -9,7 +9,9 @@
 // INT8 matrix cores with exact int32 accumulation; products with the same
 // digit weight 256^s (i + j = s) share one accumulator, so there are 2D - 1
 // accumulators per output.  A block of K k-terms keeps every accumulator
-// exact when K * min(D_A, D_B) * 2^14 <= 2^31 - 1 (|d_i d_j| <= 2^14).
+// exact when K times the extremes of one k-term's weight sum stay within
+// int32; the planner takes those extremes over the digit vectors the entries
+// can actually have (int8_bound_residues), at most D 2^14 in magnitude.
 // After each block the accumulators are folded into a binary64 residue:
 //     t = sum_s 256^s D_s mod p  (Horner's rule from the top weight down;
 //         256 t is exact in binary64 and each step is reduced with Alg. 1's

@@ -255,6 +255,42 @@ int mmp_plan(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, const mm
   }
 }
 
+static void copy_bound(const mmp::Int8Bound& b, mmp_int8_bound_t* out) {
+  out->digits = b.digits;
+  out->weight_max = b.weight_max;
+  out->weight_min = b.weight_min;
+  out->lo = b.lo;
+  out->hi = b.hi;
+  out->term_max = b.term_max;
+  out->term_min = b.term_min;
+  for (int i = 0; i < 2; i++) {
+    out->witness_max[i] = b.witness_max[i];
+    out->witness_min[i] = b.witness_min[i];
+  }
+  out->kblock = b.kblock;
+}
+
+int mmp_int8_bound(uint64_t p, int entry_bits, mmp_int8_bound_t* out) {
+  if (!out) return MMP_EINVAL;
+  if (p != 0 && entry_bits == 0 && p >= 5 && p < mmp::kPMax) {
+    copy_bound(mmp::int8_bound_residues(p), out);
+    return MMP_OK;
+  }
+  if (p == 0 && entry_bits >= 1 && entry_bits <= 62) {
+    copy_bound(mmp::int8_bound_integers(entry_bits), out);
+    return MMP_OK;
+  }
+  return MMP_EINVAL;
+}
+
+int mmp_int8_interval_bound(int digits, int64_t lo, int64_t hi, mmp_int8_bound_t* out) {
+  if (!out || digits < 1 || digits > 8 || lo > hi) return MMP_EINVAL;
+  const __int128 top = mmp::radix_top(digits), R = top / 127;  // 127 R, R = (256^D - 1) / 255
+  if ((__int128)hi > top || (__int128)lo < -128 * R) return MMP_EINVAL;
+  copy_bound(mmp::int8_bound_interval(digits, lo, hi), out);
+  return MMP_OK;
+}
+
 size_t mmp_footprint(const mmp_job* job, const mmp_plan_t* plan) {
   if (!job || job->m < 0 || job->n < 0 || job->k < 0) return 0;
   const size_t m = (size_t)job->m, n = (size_t)job->n, k = (size_t)job->k;

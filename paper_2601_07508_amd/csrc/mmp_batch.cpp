@@ -134,8 +134,8 @@ int run_batch(const std::vector<Planned>& pj, const mmp_opts* opts, size_t ws_to
 
 // CRT: workspace for the fast path, or for the reduced copies of the
 // fallback (two binary64 matrices per modulus plus their products' needs).
-bool crt_fast(int64_t k, int digits, int nprimes) {
-  return digits <= 8 && k <= int8_kblock(digits) && nprimes >= 1;
+bool crt_fast(int64_t k, int entry_bits, int nprimes) {
+  return k <= int8_bound_integers(entry_bits).kblock && nprimes >= 1;
 }
 
 }  // namespace
@@ -165,7 +165,7 @@ size_t mmp_workspace_crt(int64_t m, int64_t n, int64_t k, int entry_bits, int np
   if (m <= 0 || n <= 0 || k <= 0 || entry_bits < 1 || entry_bits > 62 || nprimes < 1) return 0;
   const int d = crt_digits(entry_bits);
   const size_t kp = (size_t)((k + 63) / 64 * 64);
-  if (crt_fast(k, d, nprimes)) return digit_planes_bytes(d, m, kp) + digit_planes_bytes(d, n, kp);
+  if (crt_fast(k, entry_bits, nprimes)) return digit_planes_bytes(d, m, kp) + digit_planes_bytes(d, n, kp);
   // fallback: per modulus, reduced A and B in binary64 (the products use the
   // planner's form; an INT8 product needs at most 7-digit planes of A and B)
   const size_t per = align_up(8 * (size_t)(m * k + k * n)) + align_up(int8_workspace_bytes(kMaxDigits, m, n, k));
@@ -207,7 +207,7 @@ int mm_modp_crt(const mmp_opts* opts, const uint64_t* A, int64_t lda, const uint
     bool owned = false;
     if (int st = acquire_workspace(ws, opts, stream, &work, &owned)) return st;
     int st = MMP_OK;
-    if (crt_fast(k, d, nprimes)) {
+    if (crt_fast(k, entry_bits, nprimes)) {
       CrtLaunch c;
       std::memset(&c, 0, sizeof(c));
       c.A = A;

@@ -148,13 +148,27 @@ int default_splits(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k);
 int launch_int8_digitize_side(int digits, int side, const double* X, int64_t rows, int64_t cols, int64_t ld,
                               int64_t kp, uint64_t p, int8_t* out, void* stream);
 int digits_for(uint64_t p);                       // ceil(bitsize(p) / 8)
-int64_t int8_kblock(int digits);                  // exact-int32 block length
+int64_t int8_kblock(int digits);                  // exact-int32 block length for any entries
+// The exact int32 block for the entries' actual digit range: the extremes of
+// one k-term's digit-weight sum, entries reaching them, and the longest block
+// of whole 64-term stages that keeps every accumulator in int32.
+struct Int8Bound {
+  int digits, weight_max, weight_min;
+  int64_t lo, hi;                  // digit values x' of the entries lie in [lo, hi]
+  int64_t term_max, term_min;      // extremes of sum_{i+j=s} a_i b_j for one k-term
+  int64_t witness_max[2], witness_min[2];  // values (a, b) in [lo, hi] reaching them
+  int64_t kblock;
+};
+Int8Bound int8_bound_interval(int digits, int64_t lo, int64_t hi);
+Int8Bound int8_bound_residues(uint64_t p);       // entries in [0, p), digits_for(p) digits
+Int8Bound int8_bound_integers(int entry_bits);   // entries in [0, 2^entry_bits)
+int64_t radix_top(int digits);                   // 127 (256^D - 1) / 255
 size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k);
 // planes made per call when A and/or B are resident (rounded up to 256 bytes)
 size_t int8_planes_bytes(int digits, int64_t m, int64_t n, int64_t k, bool res_a, bool res_b);
 // Multi-modular product of one integer pair (uint64 entries < 2^entry_bits)
 // against up to kMaxPrimesCrt moduli, all from one digit GEMM; needs
-// k <= int8_kblock(digits).
+// k <= int8_bound_integers(entry_bits).kblock.
 constexpr int kMaxPrimesCrt = 64;
 struct CrtLaunch {
   const uint64_t* A;
@@ -166,7 +180,7 @@ struct CrtLaunch {
   double* C[kMaxPrimesCrt];
   int8_t* work;  // planes of A, then of B^T (digit_planes_bytes each)
 };
-int crt_digits(int entry_bits);  // ceil((entry_bits + 1) / 8), signed digits of values < 2^entry_bits
+int crt_digits(int entry_bits);  // fewest signed digits holding every value < 2^entry_bits
 int launch_crt(int digits, const CrtLaunch& c, void* stream);
 
 // Digit planes of one product into a.work, then the digit GEMM of up to

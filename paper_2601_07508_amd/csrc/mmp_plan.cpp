@@ -331,10 +331,199 @@ int default_splits(const mmp_plan_t& pl, int64_t m, int64_t n, int64_t k) {
 }
 
 int64_t int8_kblock(int digits) {
-  // K min(D_A, D_B) 2^14 <= 2^31 - 1 keeps every int32 accumulator exact
+  // K D 2^14 <= 2^31 - 1 keeps every int32 accumulator exact for any
+  // entries (|d_i d_j| <= 2^14); int8_bound_* give the longer block that the
+  // entries' actual digit range allows
   const int64_t K = ((int64_t)1 << 31) - 1;
   const int64_t per = (int64_t)digits << 14;
   return (K / per) / 64 * 64;
+}
+
+// ---- exact int32 block of the digit GEMM ------------------------------------
+// The digit GEMM sees every entry as an integer x' in an interval [lo, hi] of
+// [-128 R, 127 R], R = (256^D - 1) / 255, written with D signed digits in
+// [-128, 127] (the low byte read as int8, then the exact carry).  Because
+// the digit set is 256 consecutive integers and 255 R < 256^D, values are
+// ordered like their digit vectors read from the top digit down, so the
+// digit vectors of [lo, hi] form a union of at most 2D + 1 boxes (a common
+// top prefix, one digit in a sub-range, the digits below it free).  One
+// k-term adds sum_{i+j=s} a_i b_j to the accumulator of weight s; within a
+// pair of boxes every a_i meets exactly one b_j, so the extremes over the
+// pair are sums of the extremes of single products over the digits' ranges,
+// which sit at range ends.  A block of K k-terms is then exact when
+// K tmax <= 2^31 - 1 and K (-tmin) <= 2^31.
+namespace {
+
+struct DigitBox {
+  int lo[8], hi[8];
+};
+
+void signed_digits(__int128 v, int D, int (&d)[8]) {
+  for (int i = 0; i < D; i++) {
+    const int di = (int)(int8_t)(uint8_t)(v & 0xff);
+    d[i] = di;
+    v = (v - di) >> 8;
+  }
+}
+
+int digit_boxes(int D, int64_t lo, int64_t hi, DigitBox* out) {
+  int L[8], H[8];
+  signed_digits(lo, D, L);
+  signed_digits(hi, D, H);
+  int t = D - 1;
+  while (t >= 0 && L[t] == H[t]) t--;
+  int nb = 0;
+  auto fixed = [&](const int* P, int above, DigitBox& b) {  // digits >= above follow P
+    for (int i = above; i < D; i++) b.lo[i] = b.hi[i] = P[i];
+    for (int i = 0; i < above; i++) {
+      b.lo[i] = -128;
+      b.hi[i] = 127;
+    }
+  };
+  if (t < 0) {  // lo == hi
+    fixed(L, 0, out[nb++]);
+    return nb;
+  }
+  if (L[t] + 1 <= H[t] - 1) {  // digit t strictly between the ends
+    DigitBox& b = out[nb++];
+    fixed(L, t, b);
+    b.lo[t] = L[t] + 1;
+    b.hi[t] = H[t] - 1;
+  }
+  // digit t = L[t]: the lower digits at or above lo's, by the first one that
+  // exceeds lo's; then lo itself
+  for (int j = t - 1; j >= 0; j--) {
+    if (L[j] == 127) continue;
+    DigitBox& b = out[nb++];
+    fixed(L, j, b);
+    b.lo[j] = L[j] + 1;
+    b.hi[j] = 127;
+  }
+  fixed(L, 0, out[nb++]);
+  // digit t = H[t]: the lower digits at or below hi's; then hi itself
+  for (int j = t - 1; j >= 0; j--) {
+    if (H[j] == -128) continue;
+    DigitBox& b = out[nb++];
+    fixed(H, j, b);
+    b.lo[j] = -128;
+    b.hi[j] = H[j] - 1;
+  }
+  fixed(H, 0, out[nb++]);
+  return nb;
+}
+
+__int128 digits_value(const int (&d)[8], int D) {
+  __int128 v = 0;
+  for (int i = D - 1; i >= 0; i--) v = v * 256 + d[i];
+  return v;
+}
+
+}  // namespace
+
+int64_t radix_top(int D) {  // 127 R: the largest value D signed digits hold
+  int64_t top = 0;
+  for (int i = 0; i < D; i++) top = top * 256 + 127;
+  return top;
+}
+
+Int8Bound int8_bound_interval(int D, int64_t lo, int64_t hi) {
+  Int8Bound r;
+  std::memset(&r, 0, sizeof(r));
+  r.digits = D;
+  r.lo = lo;
+  r.hi = hi;
+  DigitBox boxes[17];
+  const int nb = digit_boxes(D, lo, hi, boxes);
+  bool first = true;
+  for (int s = 0; s <= 2 * D - 2; s++) {
+    for (int ba = 0; ba < nb; ba++) {
+      for (int bb = 0; bb < nb; bb++) {
+        const DigitBox& A = boxes[ba];
+        const DigitBox& B = boxes[bb];
+        int64_t smax = 0, smin = 0;
+        int amax[8], bmax[8], amin[8], bmin[8];
+        for (int i = 0; i < D; i++) {
+          amax[i] = amin[i] = A.lo[i];
+          bmax[i] = bmin[i] = B.lo[i];
+        }
+        for (int i = std::max(0, s - D + 1); i <= std::min(s, D - 1); i++) {
+          const int j = s - i;
+          const int ea[2] = {A.lo[i], A.hi[i]}, eb[2] = {B.lo[j], B.hi[j]};
+          int64_t hi_ = INT64_MIN, lo_ = INT64_MAX;
+          for (int x = 0; x < 2; x++)
+            for (int y = 0; y < 2; y++) {
+              const int64_t pr = (int64_t)ea[x] * eb[y];
+              if (pr > hi_) {
+                hi_ = pr;
+                amax[i] = ea[x];
+                bmax[j] = eb[y];
+              }
+              if (pr < lo_) {
+                lo_ = pr;
+                amin[i] = ea[x];
+                bmin[j] = eb[y];
+              }
+            }
+          smax += hi_;
+          smin += lo_;
+        }
+        if (first || smax > r.term_max) {
+          r.term_max = smax;
+          r.weight_max = s;
+          r.witness_max[0] = (int64_t)digits_value(amax, D);
+          r.witness_max[1] = (int64_t)digits_value(bmax, D);
+        }
+        if (first || smin < r.term_min) {
+          r.term_min = smin;
+          r.weight_min = s;
+          r.witness_min[0] = (int64_t)digits_value(amin, D);
+          r.witness_min[1] = (int64_t)digits_value(bmin, D);
+        }
+        first = false;
+      }
+    }
+  }
+  // the longest block of whole 64-term stages within int32 at both ends
+  int64_t K = INT64_MAX;
+  if (r.term_max > 0) K = std::min<int64_t>(K, (((int64_t)1 << 31) - 1) / r.term_max);
+  if (r.term_min < 0) K = std::min<int64_t>(K, ((int64_t)1 << 31) / -r.term_min);
+  if (K == INT64_MAX) K = (int64_t)1 << 40;  // all-zero entries: any block is exact
+  r.kblock = K / 64 * 64;
+  return r;
+}
+
+// Residues mod p as the digitizer maps them: x' = x, or x - p when x exceeds
+// 127 R, with D = ceil(bitsize(p) / 8), so x' lies in [127 R + 1 - p, 127 R]
+// (or [0, p - 1] when p - 1 <= 127 R).
+Int8Bound int8_bound_residues(uint64_t p) {
+  const int D = digits_for(p);
+  const int64_t top = radix_top(D);
+  const int64_t pm1 = (int64_t)p - 1;
+  return int8_bound_interval(D, pm1 > top ? top + 1 - (int64_t)p : 0, std::min(pm1, top));
+}
+
+// Integers of the multi-modular product: [0, 2^entry_bits - 1] as they are
+// (computed once per width).
+Int8Bound int8_bound_integers(int entry_bits) {
+  static std::mutex mu;
+  static Int8Bound cache[64];
+  static bool have[64] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (!have[entry_bits]) {
+    const int D = crt_digits(entry_bits);
+    cache[entry_bits] = int8_bound_interval(D, 0, (int64_t)((((uint64_t)1) << entry_bits) - 1));
+    have[entry_bits] = true;
+  }
+  return cache[entry_bits];
+}
+
+// The fewest signed base-256 digits that hold every value below 2^entry_bits:
+// 2^entry_bits - 1 <= 127 R (at most 8 for entry_bits <= 62).
+int crt_digits(int entry_bits) {
+  const uint64_t vmax = (((uint64_t)1) << entry_bits) - 1;
+  int D = 1;
+  while (D < 8 && (uint64_t)radix_top(D) < vmax) D++;
+  return D;
 }
 
 size_t int8_workspace_bytes(int digits, int64_t m, int64_t n, int64_t k) {
@@ -386,7 +575,11 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
     out->form = MMP_FORM_INT8_WORDS;
     out->digits_a = d8;
     out->digits_b = d8;
+    // the exact block of these entries (int8_bound_residues) matters only
+    // when k exceeds the block any entries allow; shorter products run whole
+    // k as one block either way, and skip the bound's cost (about 0.1 ms)
     out->kblock_int8 = int8_kblock(d8);
+    if (k > out->kblock_int8) out->kblock_int8 = int8_bound_residues(p).kblock;
     out->q = 1.0 / (double)p;
     out->bk = 64;
     out->est_seconds = int8_seconds(m, n, k, d8);

@@ -67,8 +67,6 @@ MMP_DECLC(7)
 MMP_DECLC(8)
 #undef MMP_DECLC
 
-int crt_digits(int entry_bits) { return (entry_bits + 1 + 7) / 8; }
-
 int launch_crt(int digits, const CrtLaunch& c, void* stream) {
   switch (digits) {
     case 1: return launch_crt_1(c, stream);

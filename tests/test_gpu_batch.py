@@ -110,7 +110,7 @@ def _crt_check(A, B, primes, outs, bits):
 
 
 @pytest.mark.parametrize("bits,shape", [(60, (130, 96, 257)), (20, (65, 70, 1000)), (62, (40, 33, 64)),
-                                        (8, (20, 20, 20))])
+                                        (8, (20, 20, 20)), (15, (33, 20, 100)), (55, (40, 70, 300))])
 def test_crt_fast_path(bits, shape):
     m, n, k = shape
     primes = gen.crt_primes(count=32)
@@ -140,6 +140,27 @@ def test_crt_extreme_entries(primes):
     mmp.mm_modp_crt(dev64(A), dev64(B), primes, outs, bits)
     torch.cuda.synchronize()
     _crt_check(A, B, primes, outs, bits)
+
+
+# Widths 8D - 1 need D + 1 signed digits (2^(8D-1) - 1 > 127 (256^D - 1) / 255):
+# the entries just below 2^bits, and the witnesses of the integer block's
+# extremes over one whole block (k = K, the fast path's limit).
+@pytest.mark.parametrize("bits", [15, 23, 55, 62])
+def test_crt_widest_entries_and_block_limit(bits):
+    b = mmp.int8_bound(entry_bits=bits)
+    K = b["kblock"]
+    primes = [4503599627370449, 1125899906842597, 2147483647, 65521]
+    top = (1 << bits) - 1
+    m, n = 8, 12
+    vals = np.array([top, top - 1, top - 127, (1 << (bits - 1)), 0], dtype=np.uint64)
+    for k, A, B in ((300, vals[np.arange(m * 300) % 5].reshape(m, 300), vals[(np.arange(300 * n) * 3) % 5].reshape(300, n)),
+                    (K, np.full((m, K), b["witness_max"][0], dtype=np.uint64),
+                     np.full((K, n), b["witness_max"][1], dtype=np.uint64))):
+        say("crt widest", bits, k)
+        outs = [torch.full((m, n), -1.0, dtype=torch.float64, device="cuda") for _ in primes]
+        mmp.mm_modp_crt(dev64(A), dev64(B), primes, outs, bits)
+        torch.cuda.synchronize()
+        _crt_check(A, B, primes, outs, bits)
 
 
 def test_crt_long_k_falls_back_to_reduced_products():

@@ -1,9 +1,13 @@
-"""The benchmark workloads at full size, checked on sampled outputs.
+"""The benchmark workloads at full size, every output checked.
 
 Each product runs through the same entry point and plan as the benchmark.
-The oracle recomputes whole sampled rows and columns plus random entries
-exactly; every output is also checked to be an integer in [0, p).
-The 512^3 workload is small enough to compare in full.
+Every output is checked to be an integer in [0, p), and every output enters
+Freivalds' check with the oracle as the checker: for seeded random vectors
+x, A (B x) and C x mod p are formed by the oracle (products with one column)
+and must agree.  A wrong entry of C makes its row of C x wrong except with
+probability 1/p per trial (p prime), and two trials run.  The oracle also
+recomputes whole sampled rows and columns plus random entries exactly; the
+512^3 workload is small enough to compare in full.
 """
 
 import sys
@@ -13,6 +17,7 @@ import pytest
 
 import mmp_inputs as gen
 import oracle
+from tests import freivalds
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +72,10 @@ def _check_sampled(prob, A, B, C, nrows=2, ncols=2, nrand=512):
     assert bad.size == 0, f"{bad.size} sampled mismatches, first ({rr[bad[0]]},{cc[bad[0]]})"
 
 
+def _freivalds(p, A, B, C, seed):
+    freivalds.check(p, A, B, C.cpu().numpy(), seed)
+
+
 def test_square_512_b25_full():
     (prob,) = gen.config_problems(1)
     say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
@@ -81,17 +90,36 @@ def test_square_4096(idx):
     say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
     A, B, C = _compute(prob)
     _check_sampled(prob, A, B, C)
+    _freivalds(prob.p, A, B, C, prob.seed)
 
 
+# 8192^3 at p = 2^50 - 27: (2,2) words under the paper's bound (the benchmark's
+# headline), the same under the extended and centered bounds, and the INT8
+# digits; uniform entries and the all-(p-1) worst case
+FORMS_8192 = {"paper": {}, "extended": {"extended_block": True}, "centered": {"centered_words": True},
+              "int8": {"form": 2}}
+
+
+@pytest.mark.parametrize("form", list(FORMS_8192))
 @pytest.mark.parametrize("idx", [0, 1])
-def test_square_8192_b50_22(idx):
+def test_square_8192_b50_22(idx, form):
     prob = gen.config_problems(3)[idx]
-    say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
-    A, B, C = _compute(prob)
+    opts = FORMS_8192[form]
+    u, v = (0, 0) if form == "int8" else (prob.u, prob.v)
+    say("config", prob.tag, form, mmp.plan(prob.p, prob.m, prob.n, prob.k, u, v, **opts))
+    A, B = prob.a(), prob.b()
+    dA = torch.from_numpy(A.astype(np.float64)).cuda()
+    dB = torch.from_numpy(B.astype(np.float64)).cuda()
+    C = torch.full((prob.m, prob.n), -1.0, dtype=torch.float64, device="cuda")
+    mmp.mm_modp_async(dA, dB, C, prob.p, u, v, **opts)
+    torch.cuda.synchronize()
+    del dA, dB
     if prob.fill == "pmax":
         # (p-1)^2 = 1 mod p: every entry is k mod p
         assert bool(torch.all(C == float(prob.k % prob.p)))
-    _check_sampled(prob, A, B, C, nrows=1, ncols=1, nrand=256)
+    else:
+        _check_sampled(prob, A, B, C, nrows=1, ncols=1, nrand=256)
+        _freivalds(prob.p, A, B, C, prob.seed)
 
 
 @pytest.mark.parametrize("idx", list(range(8)))
@@ -100,6 +128,7 @@ def test_sweep_shapes(idx):
     say("config", prob.tag, mmp.plan(prob.p, prob.m, prob.n, prob.k, prob.u, prob.v))
     A, B, C = _compute(prob)
     _check_sampled(prob, A, B, C, nrows=1, ncols=1, nrand=512)
+    _freivalds(prob.p, A, B, C, prob.seed)
 
 
 def test_crt_2048_32_primes():
@@ -119,6 +148,7 @@ def test_crt_2048_32_primes():
         want = oracle.mm_modp_entries(p, A, B, rr, cc).astype(np.float64)
         got = C[torch.from_numpy(rr).cuda(), torch.from_numpy(cc).cuda()].cpu().numpy()
         assert np.array_equal(got, want), p
+        _freivalds(p, A, B, C, job.seed)  # the oracle reduces the integer entries mod p
 
 
 @pytest.mark.parametrize("bits", [26, 50])
@@ -148,3 +178,4 @@ def test_unbalanced_10923x32768x32(bits):
     torch.cuda.synchronize()
     assert all(torch.equal(outs[0], c) for c in outs[1:])
     _check_sampled(prob, A, B, outs[0], nrows=2, ncols=1, nrand=256)
+    _freivalds(prob.p, A, B, outs[0], prob.seed)

@@ -99,26 +99,34 @@ def test_int8_folds_between_blocks(p):
         assert_exact(run(p, A, B, force_kblock=kb), want)
 
 
-def test_int8_block_bound_is_the_largest_exact_one():
-    for d in range(1, 8):
-        p = gen.prev_prime(1 << (8 * d)) if d < 7 else 4503599627370449
-        kb = mmp.plan(p, 8, 8, 8, form=INT8)["kblock_int8"]
-        assert kb % 64 == 0
-        assert kb * min(d, d) * 2**14 <= 2**31 - 1 < (kb + 64) * d * 2**14
+# Entries that drive one digit-weight accumulator to the planner's exact
+# extreme on every k-term (the witnesses of mmp_int8_bound): with k = K, one
+# whole int32 block and no split, the accumulator ends at K * term_max (or
+# K * term_min).  K is the longest block of 64-term stages within int32, so
+# this reaches 99.8-99.99% of 2^31 (printed per case); 2K + 71 adds a second
+# full block, a fold in between and a ragged tail.  The CPU tests show that
+# K + 64 would wrap.
+BLOCK_PRIMES = [251, 65521, 16777213, 4294967291, 1099511627689, 281474976710597, 281474976710655,
+                1125899906842597, 4503599627370449]
 
 
-def test_int8_full_k_block_with_extreme_digits():
-    # k equal to the block length with every digit product at +2^14:
-    # entries whose digits are all -128 reach the int32 limit exactly.
-    p = 4503599627370449  # 7 digits
-    kb = mmp.plan(p, 8, 8, 8, form=INT8)["kblock_int8"]
-    x = int("80" * 6, 16)  # digits 0x80 = -128 in the low six places
-    x = x % p
-    m, n, k = 16, 16, kb
-    A = np.full((m, k), x, dtype=np.uint64)
-    B = np.full((k, n), x, dtype=np.uint64)
-    say("int8 extreme", kb)
-    assert_exact(run(p, A, B), oracle.mm_modp(p, A, B))
+@pytest.mark.parametrize("which", ["max", "min"])
+@pytest.mark.parametrize("p", BLOCK_PRIMES)
+def test_int8_block_at_its_exact_limit(p, which):
+    b = mmp.int8_bound(p)
+    K = b["kblock"]
+    assert mmp.plan(p, 16, 24, 2 * K + 71, form=INT8)["kblock_int8"] == K
+    a, c = b["witness_" + which]
+    reach = K * b["term_" + which]
+    assert -2**31 <= reach <= 2**31 - 1
+    say("int8 block limit", p, which, "K", K, "accumulator", reach, f"= {reach / 2**31:+.5f} of 2^31")
+    m, n = 16, 24
+    for k in (K, 2 * K + 71):
+        A = np.full((m, k), a % p, dtype=np.uint64)
+        B = np.full((k, n), c % p, dtype=np.uint64)
+        A[3, :] = p - 1  # other rows and columns with other digits
+        B[:, 5] = (p - 1) // 2
+        assert_exact(run(p, A, B, splits=1), oracle.mm_modp(p, A, B))
 
 
 def test_int8_strided_and_stream():

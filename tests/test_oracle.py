@@ -188,3 +188,23 @@ def _pins_pass(fn) -> bool:
 def test_pins_reject_planted_mistakes(mutant):
     assert _pins_pass(oracle.mm_modp)
     assert not _pins_pass(mutant)
+
+
+def test_freivalds_check_catches_one_wrong_entry():
+    # the whole-product check the full-size GPU tests use: an exact C passes,
+    # and a C with one entry off by one (or with two rows swapped) fails
+    from tests import freivalds
+    p = 1125899906842597
+    A = gen.random_matrix(31, 1, 300, 170, p)
+    B = gen.random_matrix(31, 2, 170, 200, p)
+    C = oracle.mm_modp(p, A, B)
+    freivalds.check(p, A, B, C, seed=5)
+    for (r, c) in [(0, 0), (299, 199), (123, 45)]:
+        bad = C.copy()
+        bad[r, c] = (int(bad[r, c]) + 1) % p
+        with pytest.raises(AssertionError, match=f"first row {r}"):
+            freivalds.check(p, A, B, bad, seed=5)
+    swapped = C.copy()
+    swapped[[10, 11]] = swapped[[11, 10]]
+    with pytest.raises(AssertionError, match="2 rows"):
+        freivalds.check(p, A, B, swapped, seed=5)
