@@ -156,7 +156,7 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
-template <int U, int V, int TM, int TN, int FE, bool PAD>
+template <int U, int V, int TM, int TN, int FE, bool PAD, bool LAZY>
 __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch bt) {
   static_assert(FE == 1 || FE == 2 || FE == 4, "reduction period");
   // which product of the batch this workgroup belongs to (uniform, scalar)
@@ -324,9 +324,22 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
   const int64_t s_end = s_begin + per_split < nstages_all ? s_begin + per_split : nstages_all;
   const int lrow = lane & 15, lk = lane >> 4;
 
-  // In-loop reduction of every accumulator (Alg. 1).  The correction-free
-  // form leaves values in [-p, 2p); when the planner could not show that a
-  // block started there stays within 2^t, the two corrections follow.
+  // In-loop reduction (Alg. 1) of one accumulator tile.  The correction-free
+  // form leaves values in [-p, 2p) (or the biased range); when the planner
+  // could not show that a block started there stays within 2^t (LAZY =
+  // false), the two corrections follow.
+  auto reduce_one = [&](d4& v) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) v[r] = fmod_lazy(v[r], p, q, bias);
+    if constexpr (!LAZY) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        double d = v[r];
+        d = (d >= p) ? d - p : d;
+        v[r] = (d < 0.0) ? d + p : d;
+      }
+    }
+  };
   auto reduce_all = [&]() {
 #pragma unroll
     for (int i = 0; i < U; i++)
@@ -335,25 +348,7 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
 #pragma unroll
         for (int x = 0; x < TM; x++)
 #pragma unroll
-          for (int y = 0; y < TN; y++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) acc[i][j][x][y][r] = fmod_lazy(acc[i][j][x][y][r], p, q, bias);
-    if (!a.lazy) {
-#pragma unroll
-      for (int i = 0; i < U; i++)
-#pragma unroll
-        for (int j = 0; j < V; j++)
-#pragma unroll
-          for (int x = 0; x < TM; x++)
-#pragma unroll
-            for (int y = 0; y < TN; y++)
-#pragma unroll
-              for (int r = 0; r < 4; r++) {
-                double d = acc[i][j][x][y][r];
-                d = (d >= p) ? d - p : d;
-                acc[i][j][x][y][r] = (d < 0.0) ? d + p : d;
-              }
-    }
+          for (int y = 0; y < TN; y++) reduce_one(acc[i][j][x][y]);
   };
 
   // Stage s is split into buffer (s - s_begin) & 1 one iteration ahead; its
@@ -369,43 +364,101 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
     if (s_begin + 1 < s_end) load_stage((s_begin + 1) * KR);
   }
   lds_barrier();
-  for (int64_t s = s_begin; s < s_end; s++) {
-    const int buf = (int)((s - s_begin) & 1);
+  // Fragments of one k-step: A's rows for every word and tile row, B's
+  // columns for every word and tile column.
+  auto read_frags = [&](int buf, int ks, double (&af)[U][TM], double (&bf)[V][TN]) {
 #pragma unroll
-    for (int ks = 0; ks < kBK / 4; ks++) {
-      double af[U][TM], bf[V][TN];
+    for (int i = 0; i < U; i++)
 #pragma unroll
-      for (int i = 0; i < U; i++)
+      for (int x = 0; x < TM; x++) af[i][x] = As[buf][i][wm + x * 16 + lrow][ks * 4 + lk];
 #pragma unroll
-        for (int x = 0; x < TM; x++) af[i][x] = As[buf][i][wm + x * 16 + lrow][ks * 4 + lk];
+    for (int j = 0; j < V; j++)
 #pragma unroll
-      for (int j = 0; j < V; j++)
+      for (int y = 0; y < TN; y++) bf[j][y] = Bs[buf][j][ks * 4 + lk][bswz(lk, wn + y * 16 + lrow)];
+  };
+  constexpr int NACC = U * V * TM * TN;
+  constexpr int kRedOps = LAZY ? 12 : 32;  // VALU operations of reduce_one (4 values)
+  // accumulator t in (i, j, x, y) order
+  auto acc_of = [&](int t) -> d4& {
+    return acc[t / (V * TM * TN)][(t / (TM * TN)) % V][(t / TN) % TM][t % TN];
+  };
+  auto mfma_one = [&](int t, const double (&af)[U][TM], const double (&bf)[V][TN]) {
+    const int i = t / (V * TM * TN), j = (t / (TM * TN)) % V, x = (t / TN) % TM, y = t % TN;
+    acc[i][j][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][x], bf[j][y], acc[i][j][x][y], 0, 0, 0);
+  };
+
+  if constexpr (FE < 4) {
+    // Blocks of FE k-steps (4 or 8 slots).  The reduction that ends a block
+    // is deferred to the start of the next one and interleaved with its
+    // first k-step, one accumulator ahead: reduce t + 1, then the MFMA on t.
+    // On gfx950 no VALU instruction issues while the SIMD's matrix pipe runs
+    // an FP64 MFMA, from the same wave or another, so reductions and MFMAs
+    // add up; the interleave keeps either wave of a SIMD ready to issue.
+    // The first block of a range reduces its initial value too (harmless:
+    // any |x| <= 2^t maps into the restart range); the last block's
+    // reduction is left to the epilogue's complete one (its partial sums are
+    // within 2^t by the block bound).
+    for (int64_t s = s_begin; s < s_end; s++) {
+      const int buf = (int)((s - s_begin) & 1);
 #pragma unroll
-        for (int y = 0; y < TN; y++) bf[j][y] = Bs[buf][j][ks * 4 + lk][bswz(lk, wn + y * 16 + lrow)];
+      for (int ks = 0; ks < kBK / 4; ks++) {
+        double af[U][TM], bf[V][TN];
+        read_frags(buf, ks, af, bf);
+        if (ks % FE == 0) {
+          reduce_one(acc_of(0));
 #pragma unroll
-      for (int i = 0; i < U; i++)
+          for (int t = 0; t < NACC; t++) {
+            if (t + 1 < NACC) reduce_one(acc_of(t + 1));
+            mfma_one(t, af, bf);
+          }
+        } else {
 #pragma unroll
-        for (int j = 0; j < V; j++)
+          for (int t = 0; t < NACC; t++) mfma_one(t, af, bf);
+        }
+        // Nudge the machine schedule toward that order: the fragment reads,
+        // then a reduction's VALU operations between MFMAs (left alone, the
+        // compiler gathers the MFMAs into bursts; hard scheduling fences
+        // enforcing the exact order measured slower).
+        __builtin_amdgcn_sched_group_barrier(0x100, U * TM + V * TN, 0);  // LDS reads
+        if (ks % FE == 0) {
+          __builtin_amdgcn_sched_group_barrier(0x002, 2 * kRedOps, 0);
 #pragma unroll
-          for (int x = 0; x < TM; x++)
+          for (int t = 0; t + 1 < NACC; t++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, kRedOps, 0);
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        } else {
+          __builtin_amdgcn_sched_group_barrier(0x008, NACC, 0);
+        }
+      }
+      if (s + 1 < s_end) {
+        store_stage(buf ^ 1);
+        if (s + 2 < s_end) load_stage((s + 2) * KR);
+      }
+      lds_barrier();
+    }
+  } else {
+    for (int64_t s = s_begin; s < s_end; s++) {
+      const int buf = (int)((s - s_begin) & 1);
 #pragma unroll
-            for (int y = 0; y < TN; y++)
-              acc[i][j][x][y] =
-                  __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][x], bf[j][y], acc[i][j][x][y], 0, 0, 0);
-      if constexpr (FE < 4) {
-        if ((ks + 1) % FE == 0) reduce_all();
-      } else {  // blocks of any whole number of k-steps, across stages
+      for (int ks = 0; ks < kBK / 4; ks++) {
+        double af[U][TM], bf[V][TN];
+        read_frags(buf, ks, af, bf);
+#pragma unroll
+        for (int t = 0; t < NACC; t++) mfma_one(t, af, bf);
+        // blocks of any whole number of k-steps, across stages
         if (++kc == kpb) {
           kc = 0;
           reduce_all();
         }
       }
+      if (s + 1 < s_end) {
+        store_stage(buf ^ 1);
+        if (s + 2 < s_end) load_stage((s + 2) * KR);
+      }
+      lds_barrier();
     }
-    if (s + 1 < s_end) {
-      store_stage(buf ^ 1);
-      if (s + 2 < s_end) load_stage((s + 2) * KR);
-    }
-    lds_barrier();
   }
 
   // Epilogue: complete reduction and Horner recombination, then one store.
@@ -451,7 +504,7 @@ inline int64_t tiles_of(const Fp64Args& a) {
   return ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN) * a.splits;
 }
 
-template <int U, int V, int ID, int FE, bool PAD>
+template <int U, int V, int ID, int FE, bool PAD, bool LAZY>
 int launch_shape(const Fp64Batch& b0, hipStream_t s) {
   constexpr bool WIDE = FE == 4 && !PAD;  // fp64_wide() of the launch's class
   constexpr int TM = TileOf<U, V, ID, WIDE>::tm, TN = TileOf<U, V, ID, WIDE>::tn;
@@ -470,7 +523,7 @@ int launch_shape(const Fp64Batch& b0, hipStream_t s) {
   b.tile_start[b.njobs] = (int)total;
   if (total <= 0) return 0;
   TimerTok* t = timer_begin("fp64_words");
-  hipExtLaunchKernelGGL((fp64_words_kernel<U, V, TM, TN, FE, PAD>), dim3((unsigned)total), dim3(kThreads), 0, s,
+  hipExtLaunchKernelGGL((fp64_words_kernel<U, V, TM, TN, FE, PAD, LAZY>), dim3((unsigned)total), dim3(kThreads), 0, s,
                         timer_start(t), timer_stop(t), 0, b);
   const int e = (int)hipGetLastError();
   timer_commit(t, e);

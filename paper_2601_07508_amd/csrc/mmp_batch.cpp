@@ -88,7 +88,7 @@ int run_batch(const std::vector<Planned>& pj, const mmp_opts* opts, size_t ws_to
   for (const Planned& x : pj) {
     const mmp_job& j = *x.job;
     if (j.m == 0 || j.n == 0 || j.k == 0 || x.plan.form != MMP_FORM_FP64_WORDS) continue;
-    groups[std::make_tuple(x.plan.u, x.plan.v, x.plan.tile, fp64_class(x.plan.slots, x.plan.kblock))].push_back(&x);
+    groups[std::make_tuple(x.plan.u, x.plan.v, x.plan.tile, fp64_class(x.plan.slots, x.plan.kblock, x.plan.lazy != 0))].push_back(&x);
   }
   for (auto& kv : groups) {
     const auto& v = kv.second;

@@ -19,23 +19,30 @@ int MMP_CAT(launch_fp64_words_, MMP_U, MMP_V)(int tile_id, const Fp64Batch& a, v
   (void)UV;
   // k-steps per in-loop reduction: S / 4 for S in {4, 8}, else 4 (whole
   // stages); padded stages when a block leaves zero slots (L < S <= 16);
-  // every product of a batch has the same class (fp64_class)
-  const int cls = fp64_class(a.job[0].S, a.job[0].L);
-  const int fe = cls >> 1;
-  const bool pad = (cls & 1) != 0;
-#define MMP_SHAPE(ID_)                                                                  \
-  if (tile_id == ID_) {                                                                 \
-    if (fe == 1) return pad ? launch_shape<MMP_U, MMP_V, ID_, 1, true>(a, s)            \
-                            : launch_shape<MMP_U, MMP_V, ID_, 1, false>(a, s);          \
-    if (fe == 2) return pad ? launch_shape<MMP_U, MMP_V, ID_, 2, true>(a, s)            \
-                            : launch_shape<MMP_U, MMP_V, ID_, 2, false>(a, s);          \
-    return pad ? launch_shape<MMP_U, MMP_V, ID_, 4, true>(a, s)                         \
-               : launch_shape<MMP_U, MMP_V, ID_, 4, false>(a, s);                       \
+  // correction-free in-loop reductions or not; every product of a batch has
+  // the same class (fp64_class)
+  const int cls = fp64_class(a.job[0].S, a.job[0].L, a.job[0].lazy != 0);
+  const int fe = cls >> 2;
+  const bool pad = (cls & 2) != 0;
+  const bool lazy = (cls & 1) != 0;
+#define MMP_FE(ID_, FE_)                                                                       \
+  if (fe == FE_) {                                                                             \
+    if (pad) return lazy ? launch_shape<MMP_U, MMP_V, ID_, FE_, true, true>(a, s)              \
+                         : launch_shape<MMP_U, MMP_V, ID_, FE_, true, false>(a, s);            \
+    return lazy ? launch_shape<MMP_U, MMP_V, ID_, FE_, false, true>(a, s)                      \
+                : launch_shape<MMP_U, MMP_V, ID_, FE_, false, false>(a, s);                    \
+  }
+#define MMP_SHAPE(ID_) \
+  if (tile_id == ID_) { \
+    MMP_FE(ID_, 1)      \
+    MMP_FE(ID_, 2)      \
+    MMP_FE(ID_, 4)      \
   }
   MMP_SHAPE(1)
   MMP_SHAPE(2)
   MMP_SHAPE(3)
 #undef MMP_SHAPE
+#undef MMP_FE
   return (int)hipErrorInvalidValue;
 }
 

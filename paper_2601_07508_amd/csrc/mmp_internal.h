@@ -208,13 +208,14 @@ struct Fp64Batch {
   int tile_start[kMaxBatch + 1];  // filled by the launcher
   Fp64Args job[kMaxBatch];
 };
-// Kernel class of a plan, 2 FE + PAD: FE = k-steps per in-loop reduction
-// (1, 2 or 4), PAD = blocks leave zero slots in a stage (L < S <= 16).
-// Jobs of one launch share it.
-inline int fp64_class(int slots, int64_t kblock) {
+// Kernel class of a plan, 4 FE + 2 PAD + LAZY: FE = k-steps per in-loop
+// reduction (1, 2 or 4), PAD = blocks leave zero slots in a stage
+// (L < S <= 16), LAZY = correction-free in-loop reductions.  Jobs of one
+// launch share it.
+inline int fp64_class(int slots, int64_t kblock, bool lazy) {
   const int fe = slots == 4 ? 1 : slots == 8 ? 2 : 4;  // 4: a k-step counter, any S = 4j >= 12
   const int pad = (slots <= kBK && kblock < slots) ? 1 : 0;
-  return 2 * fe + pad;
+  return 4 * fe + 2 * pad + (lazy ? 1 : 0);
 }
 
 // Launch the fused FP64-word kernel; returns a hipError_t value (0 = success).
