@@ -133,7 +133,7 @@ def serving(mmp, torch, gen, count, loads):
                     if arrivals is not None:
                         while time.perf_counter() - t0 < arrivals[i]:
                             time.sleep(0)
-                    tickets[i] = srv.submit(A, B, C, pr.p, wait_caller=False)  # inputs synchronised above
+                    tickets[i] = srv.submit(A, B, C, pr.p, ordered=False)  # inputs synchronised above
 
             th = threading.Thread(target=submitter)
             th.start()
@@ -156,7 +156,8 @@ def serving(mmp, torch, gen, count, loads):
            "closed_loop_gflops": round(flops / wall / 1e9, 1),
            "closed_loop_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
            "closed_loop_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-           "max_batch": stats["max_batch"], "loads": {}}
+           "max_batch": stats["max_batch"], "max_batches_in_flight": stats["max_inflight"],
+           "max_requests_in_flight": stats["max_running"], "loads": {}}
     r = gen.raw_u64(gen.stream_key(gen.BASE_SEED + 6, 9), 0, len(ops)).astype(np.float64) / 2.0**64
     gaps = -np.log1p(-np.minimum(r, 1 - 1e-16))  # unit-rate exponential
     for f in loads:
@@ -167,7 +168,9 @@ def serving(mmp, torch, gen, count, loads):
                                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                                 "mean_ms": round(float(lat.mean()) * 1e3, 3),
                                 "throughput_gflops": round(flops / wall / 1e9, 1),
-                                "launches": stats["launches"], "max_batch": stats["max_batch"]}
+                                "launches": stats["launches"], "max_batch": stats["max_batch"],
+                                "max_batches_in_flight": stats["max_inflight"],
+                                "max_requests_in_flight": stats["max_running"]}
     return out
 
 

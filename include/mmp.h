@@ -308,6 +308,10 @@ enum {
                               planner's time estimate; exercises admission,
                               queueing and latency accounting only (outputs
                               are not written) */
+  MMP_SERVER_FAIL_LAUNCHES = 2, /* testing aid: every batch fails at launch
+                              with MMP_ENOMEM before any device work, so the
+                              failure path (requests completed with that
+                              status, waiters woken) runs on the host */
   MMP_SUBMIT_NOQUEUE = 1   /* reject with MMP_EBUSY instead of queueing when
                               the request cannot be admitted at once */
 };
@@ -317,9 +321,12 @@ typedef struct {
   int64_t launches, max_batch;  /* batches launched, largest batch */
   int64_t queued, running;      /* requests waiting / in flight now */
   size_t used_bytes, peak_used_bytes, resident_bytes;
+  int64_t max_inflight;         /* most batches in flight at once */
+  int64_t max_running;          /* most requests in flight at once */
 } mmp_server_stats_t;
 
-/* Starts a server on `device` (flags: 0 or MMP_SERVER_DRY_RUN). */
+/* Starts a server on `device` (flags: 0, MMP_SERVER_DRY_RUN and/or
+ * MMP_SERVER_FAIL_LAUNCHES). */
 int mmp_server_create(mmp_server **out, int device, size_t hbm_budget,
                       int max_slots, int flags);
 
@@ -353,6 +360,15 @@ int mmp_unregister_operand(mmp_server *srv, uint64_t handle);
  * reported done. */
 int mmp_submit(mmp_server *srv, const mmp_job *job, int flags,
                uint64_t *ticket);
+
+/* mmp_submit, ordered after the work already queued on the caller's
+ * `stream` (a hipStream_t as void*): an event recorded there at submission
+ * is waited for on the device by the server's launch stream, so A, B and C
+ * may still be in production on `stream` when this is called.  The host
+ * does not block.  NULL stream: as mmp_submit.  In dry-run mode the stream
+ * is ignored. */
+int mmp_submit_after(mmp_server *srv, const mmp_job *job, int flags,
+                     void *stream, uint64_t *ticket);
 
 /* *done = 1 when the request has completed; then *status is its result
  * code and *latency_s the time from submission to completion, and the
@@ -426,8 +442,9 @@ int mmp_int8_interval_bound(int digits, int64_t lo, int64_t hi,
                             mmp_int8_bound_t *out);
 
 /* Device bytes a job occupies: its operands and result (8 (mk + kn + mn))
- * plus its word copies (FP64 words: 8 (u mk + v kn); INT8 digits:
- * da mk + db kn), per the storage cost of Section 3.3. */
+ * plus its word copies (FP64 words: 8 (u mk + v kn); INT8 digits: the
+ * digit planes as the library lays them out, about da mk + db kn with rows
+ * rounded up to 16 and k to 64), per the storage cost of Section 3.3. */
 size_t mmp_footprint(const mmp_job *job, const mmp_plan_t *plan);
 
 /* Static description of a status code (never NULL). */

@@ -432,10 +432,12 @@ def mm_modp_crt(A, B, primes, outs, entry_bits: int, stream=None, **opts):
 class MmpServerStats(ctypes.Structure):
     _fields_ = [("submitted", _i64), ("completed", _i64), ("failed", _i64), ("rejected", _i64),
                 ("launches", _i64), ("max_batch", _i64), ("queued", _i64), ("running", _i64),
-                ("used_bytes", _sz), ("peak_used_bytes", _sz), ("resident_bytes", _sz)]
+                ("used_bytes", _sz), ("peak_used_bytes", _sz), ("resident_bytes", _sz),
+                ("max_inflight", _i64), ("max_running", _i64)]
 
 
 SERVER_DRY_RUN = 1
+SERVER_FAIL_LAUNCHES = 2
 SUBMIT_NOQUEUE = 1
 
 _lib.mmp_server_create.argtypes = [ctypes.POINTER(_vp), _int, _sz, _int, _int]
@@ -454,6 +456,8 @@ _lib.mmp_prepare_operand.restype = _int
 _lib.mmp_unregister_operand.argtypes = [_vp, _u64]
 _lib.mmp_unregister_operand.restype = _int
 _lib.mmp_submit.argtypes = [_vp, ctypes.POINTER(MmpJob), _int, ctypes.POINTER(_u64)]
+_lib.mmp_submit_after.argtypes = [_vp, ctypes.POINTER(MmpJob), _int, _vp, ctypes.POINTER(_u64)]
+_lib.mmp_submit_after.restype = _int
 _lib.mmp_submit.restype = _int
 _lib.mmp_poll.argtypes = [_vp, _u64, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_dbl)]
 _lib.mmp_poll.restype = _int
@@ -468,17 +472,19 @@ class Server:
 
     Tensors passed to submit() are kept referenced until their ticket is
     reported done, so their memory cannot be released while in flight.
-    The server's streams are not ordered after the caller's: register_operand()
-    and submit() first wait for torch's current stream, so that work queued
-    there to produce A, B or C has finished before the server reads or
-    writes them (submit(..., wait_caller=False) skips the wait when the
-    caller has already synchronised).
+    submit() orders the request after the work queued so far on torch's
+    current stream (mmp_submit_after: the server's launch stream waits for
+    an event recorded there), so A, B and C may still be in production on it;
+    the host does not block.  register_operand() is synchronous and first
+    waits for torch's current stream.
     """
 
-    def __init__(self, hbm_budget: int, max_slots: int = 64, device: int = 0, dry_run: bool = False):
+    def __init__(self, hbm_budget: int, max_slots: int = 64, device: int = 0, dry_run: bool = False,
+                 fail_launches: bool = False):
         self._h = _vp()
-        _check(_lib.mmp_server_create(ctypes.byref(self._h), device, hbm_budget, max_slots,
-                                      SERVER_DRY_RUN if dry_run else 0), "mmp_server_create")
+        flags = (SERVER_DRY_RUN if dry_run else 0) | (SERVER_FAIL_LAUNCHES if fail_launches else 0)
+        _check(_lib.mmp_server_create(ctypes.byref(self._h), device, hbm_budget, max_slots, flags),
+               "mmp_server_create")
         self._keep = {}
 
     def close(self):
@@ -493,13 +499,10 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def _wait_caller(self, t):
-        import torch
-        torch.cuda.current_stream(t.device).synchronize()
-
     def register_operand(self, M, p: int, side: int) -> int:
+        import torch
         _check_mat(M, "M")
-        self._wait_caller(M)
+        torch.cuda.current_stream(M.device).synchronize()
         h = _u64()
         _check(_lib.mmp_register_operand(self._h, M.data_ptr(), M.shape[0], M.shape[1], max(M.stride(0), 1),
                                          p, side, ctypes.byref(h)), "mmp_register_operand")
@@ -510,20 +513,27 @@ class Server:
         _check(_lib.mmp_unregister_operand(self._h, handle), "mmp_unregister_operand")
         self._keep.pop(("operand", handle), None)
 
-    def submit_raw(self, job: MmpJob, noqueue: bool = False, keep=None) -> int:
+    def submit_raw(self, job: MmpJob, noqueue: bool = False, keep=None, stream=None) -> int:
+        """mmp_submit_after with a raw job; stream: a torch stream (None: no ordering)."""
         t = _u64()
-        _check(_lib.mmp_submit(self._h, ctypes.byref(job), SUBMIT_NOQUEUE if noqueue else 0, ctypes.byref(t)),
-               "mmp_submit")
+        sp = _vp(stream.cuda_stream) if stream is not None else _vp()
+        _check(_lib.mmp_submit_after(self._h, ctypes.byref(job), SUBMIT_NOQUEUE if noqueue else 0, sp,
+                                     ctypes.byref(t)), "mmp_submit_after")
         if keep is not None:
             self._keep[t.value] = keep
         return t.value
 
-    def submit(self, A, B, C, p: int, u: int = 0, v: int = 0, noqueue: bool = False,
-               wait_caller: bool = True) -> int:
+    def submit(self, A, B, C, p: int, u: int = 0, v: int = 0, noqueue: bool = False, stream=None,
+               ordered: bool = True) -> int:
+        """Queues C = A B mod p after the work on `stream` (default: torch's
+        current stream); ordered=False skips the ordering when the caller has
+        already synchronised the device work that writes A, B and C."""
+        import torch
         arr = _jobs_array([(A, B, C, p, u, v)])
-        if wait_caller:
-            self._wait_caller(C)
-        return self.submit_raw(arr[0], noqueue, keep=(A, B, C))
+        s = None
+        if ordered:
+            s = stream if stream is not None else torch.cuda.current_stream(C.device)
+        return self.submit_raw(arr[0], noqueue, keep=(A, B, C), stream=s)
 
     def poll(self, ticket: int):
         """None while running; else (status, latency_s)."""

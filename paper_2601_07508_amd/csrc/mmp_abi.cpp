@@ -297,7 +297,7 @@ size_t mmp_footprint(const mmp_job* job, const mmp_plan_t* plan) {
   size_t bytes = 8 * (m * k + k * n + m * n);
   if (plan) {
     if (plan->form == MMP_FORM_INT8_WORDS)
-      bytes += (size_t)plan->digits_a * m * k + (size_t)plan->digits_b * k * n;
+      bytes += mmp::int8_planes_bytes(plan->digits_a, job->m, job->n, job->k, false, false);
     else
       bytes += 8 * ((size_t)plan->u * m * k + (size_t)plan->v * k * n);
   }

@@ -64,6 +64,7 @@ struct Request {
   const Operand* res_a = nullptr;
   const Operand* res_b = nullptr;
   int solo_splits = 1;  // split-K when launched alone (the planner's choice)
+  hipEvent_t after = nullptr;  // recorded on the caller's stream at submission
 };
 
 struct InFlight {
@@ -80,6 +81,7 @@ struct mmp_server {
   size_t budget = 0;
   int max_slots = 0;
   bool dry_run = false;
+  bool fail_launches = false;  // testing aid (MMP_SERVER_FAIL_LAUNCHES)
   std::vector<hipStream_t> streams;
   std::vector<int> stream_load;
 
@@ -109,20 +111,27 @@ struct mmp_server {
     return nullptr;
   }
 
+  // The request's footprint: operands, result and word copies; for the
+  // INT8 form exactly the digit planes the launch allocates (resident planes
+  // are not counted again), and the k-range residues of a lone launch.
   size_t request_footprint(const Request& r) const {
-    mmp_plan_t pl = r.plan;
-    size_t fp = mmp_footprint(&r.job, &pl);
-    // digit planes already resident are not counted again
+    const mmp_job& j = r.job;
+    size_t fp;
     if (r.plan.form == MMP_FORM_INT8_WORDS) {
-      if (r.res_a) fp -= (size_t)r.plan.digits_a * (size_t)(r.job.m * r.job.k);
-      if (r.res_b) fp -= (size_t)r.plan.digits_b * (size_t)(r.job.k * r.job.n);
+      fp = 8 * ((size_t)(j.m * j.k) + (size_t)(j.k * j.n) + (size_t)(j.m * j.n));
+      fp += int8_planes_bytes(r.plan.digits_a, j.m, j.n, j.k, r.res_a != nullptr, r.res_b != nullptr);
+    } else {
+      mmp_plan_t pl = r.plan;
+      fp = mmp_footprint(&j, &pl);
     }
-    if (r.solo_splits > 1) fp += 8 * (size_t)r.solo_splits * (size_t)(r.job.m * r.job.n);  // k-range residues
+    if (r.solo_splits > 1) fp += 8 * (size_t)r.solo_splits * (size_t)(j.m * j.n);  // k-range residues
     return fp;
   }
 
   // ---------------------------------------------------------------- scheduler
-  void launch_locked(std::vector<uint64_t>& batch) {
+  // Launches one admitted batch; returns true when the launch failed and
+  // its requests were completed with the error (waiters must be woken).
+  bool launch_locked(std::vector<uint64_t>& batch) {
     // least busy stream
     int s = (int)(std::min_element(stream_load.begin(), stream_load.end()) - stream_load.begin());
     InFlight f;
@@ -138,6 +147,10 @@ struct mmp_server {
     }
     stats.launches += 1;
     stats.max_batch = std::max<int64_t>(stats.max_batch, (int64_t)batch.size());
+    if (fail_launches) {
+      for (uint64_t t : batch) finish_locked(reqs[t], MMP_ENOMEM, now_s());
+      return true;
+    }
     if (dry_run) {
       // no device work: the batch "runs" for the planner's estimate after
       // whatever is already queued on its stream
@@ -150,14 +163,22 @@ struct mmp_server {
       if (!err) err = (int)hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
       if (!err) err = (int)hipEventRecord(f.ev, streams[s]);
       if (err) {
+        // part of the batch may be enqueued already: let it drain before
+        // its buffers and footprint are released
+        (void)hipStreamSynchronize(streams[s]);
         const int st = err < 0 ? err : hip_status(err);
         for (uint64_t t : batch) finish_locked(reqs[t], st, now_s());
         if (f.ev) (void)hipEventDestroy(f.ev);
-        return;
+        return true;
       }
     }
     stream_load[s] += 1;
     inflight.push_back(f);
+    stats.max_inflight = std::max<int64_t>(stats.max_inflight, (int64_t)inflight.size());
+    int64_t running = 0;
+    for (auto& g : inflight) running += (int64_t)g.tickets.size();
+    stats.max_running = std::max<int64_t>(stats.max_running, running);
+    return false;
   }
 
   // Enqueues the batch on stream s; returns a hipError_t (> 0) or a
@@ -192,6 +213,10 @@ struct mmp_server {
       }
       ws += (need + 255) / 256 * 256;
     }
+    // the callers' production of A, B and C comes first (mmp_submit_after)
+    for (uint64_t t : batch)
+      if (reqs[t].after)
+        if (int e = (int)hipStreamWaitEvent(s, reqs[t].after, 0)) return e;
     void* work = nullptr;
     bool owned = false;
     if (int st = acquire_workspace(ws, nullptr, s, &work, &owned)) return st;
@@ -209,7 +234,7 @@ struct mmp_server {
         Fp64Args a = make_fp64_args(r.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc);
         a.splits = splits[i];
         a.partial = partial;
-        f64[std::make_tuple(r.plan.u, r.plan.v, r.plan.tile, fp64_class(r.plan.slots, r.plan.kblock))].push_back(a);
+        f64[std::make_tuple(r.plan.u, r.plan.v, r.plan.tile, fp64_class(r.plan.slots, r.plan.kblock, r.plan.lazy != 0))].push_back(a);
       } else {
         Int8Args g = make_int8_args(r.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc,
                                     (int8_t*)work + offs[i]);
@@ -249,6 +274,10 @@ struct mmp_server {
     if (r.state == 1) {
       used -= r.footprint;
       slots_used -= 1;
+    }
+    if (r.after) {  // its wait was enqueued before the batch's work, which has completed
+      (void)hipEventDestroy(r.after);
+      r.after = nullptr;
     }
     r.state = 2;
     r.status = status;
@@ -305,10 +334,10 @@ struct mmp_server {
     (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
-      const bool retired = retire_locked();
+      bool finished = retire_locked();
       std::vector<uint64_t> batch;
-      if (admit_locked(batch)) launch_locked(batch);
-      if (retired) cv_done.notify_all();
+      if (admit_locked(batch) && launch_locked(batch)) finished = true;
+      if (finished) cv_done.notify_all();
       if (stop && queue.empty() && inflight.empty()) break;
       if (inflight.empty() && queue.empty()) {
         cv_sched.wait(lk, [&] { return stop || !queue.empty(); });
@@ -325,13 +354,15 @@ extern "C" {
 
 int mmp_server_create(mmp_server** out, int device, size_t hbm_budget, int max_slots, int flags) {
   try {
-    if (!out || max_slots < 1 || hbm_budget == 0 || (flags & ~MMP_SERVER_DRY_RUN)) return MMP_EINVAL;
+    if (!out || max_slots < 1 || hbm_budget == 0 || (flags & ~(MMP_SERVER_DRY_RUN | MMP_SERVER_FAIL_LAUNCHES)))
+      return MMP_EINVAL;
     *out = nullptr;
     auto* s = new mmp_server();
     s->device = device;
     s->budget = hbm_budget;
     s->max_slots = max_slots;
     s->dry_run = (flags & MMP_SERVER_DRY_RUN) != 0;
+    s->fail_launches = (flags & MMP_SERVER_FAIL_LAUNCHES) != 0;
     const int nstreams = 4;
     s->stream_load.assign(nstreams, 0);
     if (!s->dry_run) {
@@ -429,6 +460,11 @@ int mmp_unregister_operand(mmp_server* s, uint64_t handle) {
 }
 
 int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
+  return mmp_submit_after(s, job, flags, nullptr, ticket);
+}
+
+int mmp_submit_after(mmp_server* s, const mmp_job* job, int flags, void* stream, uint64_t* ticket) {
+  hipEvent_t after = nullptr;
   try {
     if (!s || !job || !ticket || (flags & ~MMP_SUBMIT_NOQUEUE)) return MMP_EINVAL;
     const mmp_job& j = *job;
@@ -475,6 +511,14 @@ int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
       s->stats.rejected += 1;
       return MMP_EBUSY;
     }
+    if (stream && !s->dry_run) {
+      if (int e = (int)hipEventCreateWithFlags(&after, hipEventDisableTiming)) return hip_status(e);
+      if (int e = (int)hipEventRecord(after, (hipStream_t)stream)) {
+        (void)hipEventDestroy(after);
+        return hip_status(e);
+      }
+      r.after = after;
+    }
     r.ticket = s->next_ticket++;
     r.t_submit = now_s();
     s->stats.submitted += 1;
@@ -485,6 +529,7 @@ int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
     s->cv_sched.notify_all();
     return MMP_OK;
   } catch (...) {
+    if (after) (void)hipEventDestroy(after);
     return MMP_ENOMEM;
   }
 }

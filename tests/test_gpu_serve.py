@@ -198,3 +198,63 @@ def test_resident_b_operand():
             assert np.array_equal(C.cpu().numpy(), oracle.mm_modp(p, A, B).astype(np.float64))
         srv.unregister_operand(h)
         assert srv.stats()["resident_bytes"] == 0
+
+
+def test_requests_run_concurrently():
+    # a long product keeps the device busy while short ones arrive: they are
+    # launched beside it as batches of their own, so several batches (and
+    # requests) are in flight at once
+    p = 1099511627689
+    big = (2048, 2048, 8192)
+    A = gen.random_matrix(51, 1, big[0], big[2], p)
+    B = gen.random_matrix(51, 2, big[2], big[1], p)
+    dA, dB = dev(A), dev(B)
+    Cbig = torch.full((big[0], big[1]), -1.0, dtype=torch.float64, device="cuda")
+    small = []
+    for i in range(8):
+        a = gen.random_matrix(60 + i, 1, 64, 96, p)
+        b = gen.random_matrix(60 + i, 2, 96, 80, p)
+        small.append((a, b, dev(a), dev(b), torch.full((64, 80), -1.0, dtype=torch.float64, device="cuda")))
+    torch.cuda.synchronize()
+    with mmp.Server(hbm_budget=16 << 30, max_slots=16) as srv:
+        tickets = [srv.submit(dA, dB, Cbig, p)]
+        for _, _, da, db, c in small:
+            tickets.append(srv.submit(da, db, c, p))
+        for t in tickets:
+            assert srv.wait(t, 60.0)[0] == 0
+        st = srv.stats()
+    say("concurrency", st)
+    assert st["max_inflight"] >= 2 and st["max_running"] >= 2
+    rows = np.array([0, 1000, 2047]), np.array([0, 777, 2047])
+    want = oracle.mm_modp_entries(p, A, B, *rows).astype(np.float64)
+    assert np.array_equal(Cbig[torch.from_numpy(rows[0]).cuda(), torch.from_numpy(rows[1]).cuda()].cpu().numpy(), want)
+    for a, b, _, _, c in small:
+        assert np.array_equal(c.cpu().numpy(), oracle.mm_modp(p, a, b).astype(np.float64))
+
+
+def test_submit_is_ordered_after_the_callers_stream():
+    # A, B and C are produced on torch's stream behind long work; submit()
+    # does not block the host, and the server's launch waits for that work
+    p = 1125899906842597
+    m, n, k = 128, 96, 512
+    A = gen.random_matrix(71, 1, m, k, p)
+    B = gen.random_matrix(71, 2, k, n, p)
+    hA = torch.from_numpy(A.astype(np.float64)).pin_memory()
+    hB = torch.from_numpy(B.astype(np.float64)).pin_memory()
+    dA = torch.zeros((m, k), dtype=torch.float64, device="cuda")
+    dB = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    C = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+    X = torch.randn((4096, 4096), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    with mmp.Server(hbm_budget=4 << 30, max_slots=8) as srv:
+        for rep in range(3):
+            for _ in range(6):  # a few milliseconds of queued work first
+                X = torch.mm(X, X) * 1e-3
+            dA.copy_(hA, non_blocking=True)
+            dB.copy_(hB, non_blocking=True)
+            C.fill_(-1.0)
+            t = srv.submit(dA, dB, C, p)
+            assert srv.wait(t, 60.0)[0] == 0
+            assert np.array_equal(C.cpu().numpy(), oracle.mm_modp(p, A, B).astype(np.float64)), rep
+            dA.zero_()
+            dB.zero_()

@@ -111,3 +111,33 @@ def test_invalid_submissions():
     assert lib.mmp_server_create(ctypes.byref(h), 0, 0, 4, 1) == -1
     assert lib.mmp_server_create(ctypes.byref(h), 0, 1 << 20, 0, 1) == -1
     assert lib.mmp_server_create(ctypes.byref(h), 0, 1 << 20, 4, 8) == -1
+
+
+def test_failed_launch_wakes_waiters():
+    # every launch fails on the host (testing flag): the request completes
+    # with MMP_ENOMEM and a wait without a time limit returns
+    import threading
+    with mmp.Server(hbm_budget=1 << 30, max_slots=4, dry_run=True, fail_launches=True) as srv:
+        t = srv.submit_raw(job(64, 64, 64, 0x10000000))
+        out = {}
+        th = threading.Thread(target=lambda: out.update(r=srv.wait(t, -1.0)), daemon=True)
+        th.start()
+        th.join(10.0)
+        assert not th.is_alive(), "mmp_wait(-1) did not return after a failed launch"
+        assert out["r"][0] == -4
+        st = srv.stats()
+        assert st["failed"] == 1 and st["used_bytes"] == 0 and st["running"] == 0
+        # the server keeps serving: later requests fail the same way, promptly
+        t2 = srv.submit_raw(job(8, 8, 8, 0x20000000))
+        assert srv.wait(t2, 5.0)[0] == -4
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 5, 3), (33, 70, 65), (100, 1, 130), (5, 300, 63)])
+def test_footprint_covers_the_digit_planes(shape):
+    # the admitted footprint is at least what an INT8-form launch allocates
+    # (planes with rows rounded up to 16 and k to 64), for every digit count
+    m, n, k = shape
+    for p in (251, 65521, 16777213, 2147483647, 1099511627689, 281474976710597, 4503599627370449):
+        pl = mmp.plan(p, m, n, k, form=mmp.FORM_INT8_WORDS, splits=1)
+        fp = mmp.footprint(p, m, n, k, form=mmp.FORM_INT8_WORDS, splits=1)
+        assert fp - 8 * (m * k + k * n + m * n) >= pl["workspace_bytes"], (p, shape)
