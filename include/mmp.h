@@ -365,8 +365,8 @@ int mmp_submit(mmp_server *srv, const mmp_job *job, int flags,
  * `stream` (a hipStream_t as void*): an event recorded there at submission
  * is waited for on the device by the server's launch stream, so A, B and C
  * may still be in production on `stream` when this is called.  The host
- * does not block.  NULL stream: as mmp_submit.  In dry-run mode the stream
- * is ignored. */
+ * does not block.  NULL is the null stream, as everywhere in this library.
+ * In dry-run mode the stream is ignored. */
 int mmp_submit_after(mmp_server *srv, const mmp_job *job, int flags,
                      void *stream, uint64_t *ticket);
 

@@ -514,11 +514,15 @@ class Server:
         self._keep.pop(("operand", handle), None)
 
     def submit_raw(self, job: MmpJob, noqueue: bool = False, keep=None, stream=None) -> int:
-        """mmp_submit_after with a raw job; stream: a torch stream (None: no ordering)."""
+        """A raw job: mmp_submit_after on a torch stream, or mmp_submit (no
+        ordering) with stream=None."""
         t = _u64()
-        sp = _vp(stream.cuda_stream) if stream is not None else _vp()
-        _check(_lib.mmp_submit_after(self._h, ctypes.byref(job), SUBMIT_NOQUEUE if noqueue else 0, sp,
-                                     ctypes.byref(t)), "mmp_submit_after")
+        flags = SUBMIT_NOQUEUE if noqueue else 0
+        if stream is None:
+            _check(_lib.mmp_submit(self._h, ctypes.byref(job), flags, ctypes.byref(t)), "mmp_submit")
+        else:  # torch's default stream is the null stream (handle 0)
+            _check(_lib.mmp_submit_after(self._h, ctypes.byref(job), flags, _vp(stream.cuda_stream),
+                                         ctypes.byref(t)), "mmp_submit_after")
         if keep is not None:
             self._keep[t.value] = keep
         return t.value

@@ -459,11 +459,8 @@ int mmp_unregister_operand(mmp_server* s, uint64_t handle) {
   return MMP_OK;
 }
 
-int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
-  return mmp_submit_after(s, job, flags, nullptr, ticket);
-}
-
-int mmp_submit_after(mmp_server* s, const mmp_job* job, int flags, void* stream, uint64_t* ticket) {
+static int submit_impl(mmp_server* s, const mmp_job* job, int flags, bool ordered, void* stream,
+                       uint64_t* ticket) {
   hipEvent_t after = nullptr;
   try {
     if (!s || !job || !ticket || (flags & ~MMP_SUBMIT_NOQUEUE)) return MMP_EINVAL;
@@ -511,7 +508,7 @@ int mmp_submit_after(mmp_server* s, const mmp_job* job, int flags, void* stream,
       s->stats.rejected += 1;
       return MMP_EBUSY;
     }
-    if (stream && !s->dry_run) {
+    if (ordered && !s->dry_run) {  // a NULL stream is the null stream
       if (int e = (int)hipEventCreateWithFlags(&after, hipEventDisableTiming)) return hip_status(e);
       if (int e = (int)hipEventRecord(after, (hipStream_t)stream)) {
         (void)hipEventDestroy(after);
@@ -532,6 +529,14 @@ int mmp_submit_after(mmp_server* s, const mmp_job* job, int flags, void* stream,
     if (after) (void)hipEventDestroy(after);
     return MMP_ENOMEM;
   }
+}
+
+int mmp_submit(mmp_server* s, const mmp_job* job, int flags, uint64_t* ticket) {
+  return submit_impl(s, job, flags, false, nullptr, ticket);
+}
+
+int mmp_submit_after(mmp_server* s, const mmp_job* job, int flags, void* stream, uint64_t* ticket) {
+  return submit_impl(s, job, flags, true, stream, ticket);
 }
 
 static int report(mmp_server* s, std::unordered_map<uint64_t, Request>::iterator it, int* status, double* latency) {
