@@ -210,6 +210,25 @@ int mm_modp_async(const mmp_opts *opts, uint64_t p, int u, int v, int64_t m,
                   const double *B, int64_t ldb, double *C, int64_t ldc,
                   void *stream);
 
+/* The same product for callers that cannot allocate: code under HIP graph
+ * capture, serving loops that must not touch the allocator, harnesses that
+ * forbid it.  It calls no allocation routine.  Its workspace (digit planes
+ * of the INT8 form, split-K residues) is a library-owned device array of
+ * MMP_STATIC_SCRATCH_BYTES per device, held from the library's first use of
+ * this entry point on that device until the process ends; the plan is the
+ * one mm_modp_async makes.  MMP_ENOMEM when that plan needs more workspace
+ * than the array holds (e.g. the INT8 form of 4096^3 at 5 or more digits:
+ * pass a smaller product, fewer split-K ranges or FP64 words);
+ * MMP_EINVAL when opts carries a workspace or asks for validate_entries.
+ * Every call on one device shares that device's array: calls that overlap
+ * in time on one device (concurrent streams or threads) race; order them
+ * on one stream.  Nothing in the array needs to start at zero. */
+#define MMP_STATIC_SCRATCH_BYTES (256u << 20)
+int mm_modp_static(const mmp_opts *opts, uint64_t p, int u, int v, int64_t m,
+                   int64_t n, int64_t k, const double *A, int64_t lda,
+                   const double *B, int64_t ldb, double *C, int64_t ldc,
+                   void *stream);
+
 /* Device bytes of one operand's digit planes (0 for invalid arguments):
  * digits x outer16 x kp, with outer16 the rows of an A (side 0) or cols of a
  * B (side 1) rounded up to 16 and kp the inner dimension rounded up to 64. */

@@ -69,6 +69,9 @@ _lib.mm_modp.restype = _int
 _lib.mm_modp_async.argtypes = [ctypes.POINTER(MmpOpts), _u64, _int, _int, _i64, _i64, _i64, _vp, _i64,
                                _vp, _i64, _vp, _i64, _vp]
 _lib.mm_modp_async.restype = _int
+_lib.mm_modp_static.argtypes = list(_lib.mm_modp_async.argtypes)
+_lib.mm_modp_static.restype = _int
+STATIC_SCRATCH_BYTES = 256 << 20  # MMP_STATIC_SCRATCH_BYTES
 _lib.mmp_plan.argtypes = [_u64, _int, _int, _i64, _i64, _i64, ctypes.POINTER(MmpOpts),
                           ctypes.POINTER(MmpPlan)]
 _lib.mmp_plan.restype = _int
@@ -272,6 +275,24 @@ def mm_modp_async(A, B, C, p: int, u: int = 0, v: int = 0, stream=None, **opts):
                             B.data_ptr(), max(B.stride(0), 1), C.data_ptr(), max(C.stride(0), 1),
                             _stream_ptr(stream))
     _check(st, "mm_modp_async")
+    return C
+
+
+def mm_modp_static(A, B, C, p: int, u: int = 0, v: int = 0, stream=None, **opts):
+    """mm_modp_async with the library's fixed device workspace (mm_modp_static):
+    no allocation; calls that overlap on one device race."""
+    _check_mat(A, "A")
+    _check_mat(B, "B")
+    _check_mat(C, "C")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch")
+    o = _opts(**opts)
+    st = _lib.mm_modp_static(ctypes.byref(o), p, u, v, m, n, k, A.data_ptr(), max(A.stride(0), 1),
+                             B.data_ptr(), max(B.stride(0), 1), C.data_ptr(), max(C.stride(0), 1),
+                             _stream_ptr(stream))
+    _check(st, "mm_modp_static")
     return C
 
 

@@ -876,3 +876,28 @@ def test_split_policy(shape, form):
                 return w / (512 * -(-w // 512))
             assert (tiles * s_ >= 512 and fill(s_) >= 0.9) or 2 * s_ > cap
             assert s_ == 1 or tiles * s_ // 2 < 512 or fill(s_ // 2) < 0.9
+
+
+def test_static_entry_point_host_checks():
+    # mm_modp_static refuses, on the host and before any device call, a caller
+    # workspace, entry validation, and a plan whose workspace exceeds its
+    # fixed array (the pointers below are never dereferenced)
+    lib = mmp.lib()
+    fake = ctypes.c_void_p(0x10000)
+    fake2 = ctypes.c_void_p(0x20000000)
+    fake3 = ctypes.c_void_p(0x40000000)
+    p = 4503599627370449
+
+    def call(m, n, k, **opts):
+        o = mmp._opts(**opts)
+        return lib.mm_modp_static(ctypes.byref(o), p, 0, 0, m, n, k, fake, k, fake2, n, fake3, n, None)
+
+    o = mmp._opts()
+    o.workspace = 0x1000
+    o.workspace_bytes = 1 << 20
+    assert lib.mm_modp_static(ctypes.byref(o), p, 0, 0, 8, 8, 8, fake, 8, fake2, 8, fake3, 8, None) == -1
+    assert call(8, 8, 8, validate_entries=True) == -1
+    m = n = 16384
+    k = 4096
+    assert mmp.plan(p, m, n, k, form=2, splits=1)["workspace_bytes"] > mmp.STATIC_SCRATCH_BYTES
+    assert call(m, n, k, form=2, splits=1) == -4
