@@ -454,7 +454,52 @@ def extra_legs(args, mmp, torch, gen, prob, dA, dB, dC):
         out[pr.tag] = {"p": pr.p, "shape": [pr.m, pr.n, pr.k], "legs": recs}
         del a, b, ref
     torch.cuda.empty_cache()
+    log("batched mix")
+    out["batched_64_mixed"] = batched_mix(mmp, torch, gen, steps)
+    torch.cuda.empty_cache()
     return out
+
+
+def batched_mix(mmp, torch, gen, steps, count=64):
+    """64 uneven products in one mm_modp_batched call (INT8 digits): m, n, k
+    log-uniform in [64, 4096], bitsizes uniform in [20, 52] (digit counts
+    3..7), entries uniform on the device.  The one-launch form (digit planes
+    of all products in one launch, their GEMM in one persistent launch)
+    against the grouped form (planes per product, a GEMM per digit count and
+    16 products); outputs must agree."""
+    reqs = gen.serve_stream(count, 1.0, seed=gen.BASE_SEED + 8)
+    jobs, outs = [], {}
+    flops = 0.0
+    for r in reqs:
+        pr = r.problem
+        g = torch.Generator(device="cuda")
+        g.manual_seed(pr.seed)
+        A = torch.randint(0, pr.p, (pr.m, pr.k), generator=g, device="cuda", dtype=torch.int64).double()
+        B = torch.randint(0, pr.p, (pr.k, pr.n), generator=g, device="cuda", dtype=torch.int64).double()
+        jobs.append([A, B, None, pr.p, 0, 0])
+        flops += 2.0 * pr.m * pr.n * pr.k
+    rec = {"products": count, "bits": sorted({r.problem.p.bit_length() for r in reqs}),
+           "digit_counts": sorted({(r.problem.p.bit_length() + 7) // 8 for r in reqs}),
+           "total_2mnk": flops}
+    for name, mode in (("one_launch", 0), ("grouped", 1)):
+        Cs = [torch.empty((j[0].shape[0], j[1].shape[1]), dtype=torch.float64, device="cuda") for j in jobs]
+        js = [(j[0], j[1], C, j[3], 0, 0) for j, C in zip(jobs, Cs)]
+        ws = torch.empty(max(mmp.workspace_batched(js, form=2), 1), dtype=torch.uint8, device="cuda")
+        call = lambda: mmp.mm_modp_batched(js, workspace=ws, form=2, batch_launch=mode)
+        ms = _time(torch, call, 2, steps)
+        mmp.timers_read(reset=True)
+        mmp.timers_enable(True)
+        call()
+        torch.cuda.synchronize()
+        mmp.timers_enable(False)
+        ph = mmp.timers_read(reset=True)
+        rec[name] = {"ms": round(ms, 4), "eff_gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                     "launches": sum(v[0] for v in ph.values()),
+                     "phases_ms": {k: round(v[1], 4) for k, v in ph.items()}}
+        outs[name] = Cs
+        del ws
+    rec["identical"] = all(torch.equal(a, b) for a, b in zip(outs["one_launch"], outs["grouped"]))
+    return rec
 
 
 def main():

@@ -128,7 +128,14 @@ typedef struct {
                              p/2 + 4 + L W <= 2^t (W: the product of the two
                              word bounds).  Exclusive with extended_block and
                              strict_fmod.  0: the paper's words. */
-  int reserved[1];        /* must be zero */
+  int batch_launch;       /* mm_modp_batched, INT8-form products:
+                             0 = one launch of the digit planes and one of
+                             the digit GEMM for every 64 products, whatever
+                             their digit counts, when the batch has two or
+                             more; 1 = per digit count (planes per product,
+                             then one GEMM per digit count and 16
+                             products); 2 = the one-launch form always.
+                             Other entry points: must be zero. */
   const mmp_operand_t *prepared_a; /* mm_modp_async only: A's digit planes
                              from mmp_prepare_operand (same p and shape);
                              the product then takes the

@@ -41,7 +41,7 @@ class MmpOperand(ctypes.Structure):
 class MmpOpts(ctypes.Structure):
     _fields_ = [("form", _int), ("validate_entries", _int), ("tile", _int), ("strict_fmod", _int),
                 ("force_kblock", _i64), ("workspace", _vp), ("workspace_bytes", _sz), ("extended_block", _int),
-                ("splits", _int), ("centered_words", _int), ("reserved", _int * 1),
+                ("splits", _int), ("centered_words", _int), ("batch_launch", _int),
                 ("prepared_a", ctypes.POINTER(MmpOperand)), ("prepared_b", ctypes.POINTER(MmpOperand))]
 
 
@@ -171,8 +171,9 @@ def strerror(status: int) -> str:
 
 def _opts(form=FORM_AUTO, force_kblock=0, validate_entries=False, tile=0, strict_fmod=False,
           workspace=None, extended_block=False, splits=0, centered_words=False, prepared_a=None,
-          prepared_b=None):
+          prepared_b=None, batch_launch=0):
     o = MmpOpts()
+    o.batch_launch = batch_launch
     if prepared_a is not None:  # a PreparedOperand (its struct lives as long as it does)
         o.prepared_a = ctypes.pointer(prepared_a.desc)
     if prepared_b is not None:

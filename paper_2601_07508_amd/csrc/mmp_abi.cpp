@@ -309,6 +309,7 @@ int mm_modp_async(const mmp_opts* opts, uint64_t p, int u, int v, int64_t m, int
                   void* stream) {
   try {
     if (int st = check_product_args(m, n, k, A, lda, B, ldb, C, ldc)) return st;
+    if (opts && opts->batch_launch) return MMP_EINVAL;  // a batch option
     const mmp_operand_t* pa = opts ? opts->prepared_a : nullptr;
     const mmp_operand_t* pb = opts ? opts->prepared_b : nullptr;
     mmp_plan_t pl;

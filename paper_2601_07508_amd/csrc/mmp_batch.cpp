@@ -112,6 +112,27 @@ int run_batch(const std::vector<Planned>& pj, const mmp_opts* opts, size_t ws_to
   bool owned = false;
   if (int st = acquire_workspace(ws_total, opts, stream, &work, &owned)) return st;
   int err = 0;
+  // the one-launch form: planes of up to 64 products in one launch, their
+  // digit GEMM in one persistent launch
+  const int mode = opts ? opts->batch_launch : 0;
+  std::vector<Int8Args> all;
+  std::vector<int> all_digits;
+  for (const Planned& x : pj) {
+    const mmp_job& j = *x.job;
+    if (j.m == 0 || j.n == 0 || j.k == 0 || x.plan.form != MMP_FORM_INT8_WORDS) continue;
+    all.push_back(make_int8_args(x.plan, j.m, j.n, j.k, j.A, j.lda, j.B, j.ldb, j.C, j.ldc,
+                                 (int8_t*)work + x.ws_offset));
+    all_digits.push_back(x.plan.digits_a);
+  }
+  if (mode == 2 || (mode == 0 && all.size() >= 2)) {
+    for (size_t c = 0; c < all.size() && !err; c += kMaxMixedBatch) {
+      const int nj = (int)std::min<size_t>(kMaxMixedBatch, all.size() - c);
+      err = launch_int8_batch(all.data() + c, all_digits.data() + c, nj, stream);
+    }
+    const int st = hip_status(err);
+    const int st2 = release_workspace(work, owned, stream);
+    return st ? st : st2;
+  }
   std::map<int, std::vector<Int8Args>> by_digits;
   for (const Planned& x : pj) {
     const mmp_job& j = *x.job;
@@ -179,8 +200,7 @@ int mm_modp_crt(const mmp_opts* opts, const uint64_t* A, int64_t lda, const uint
     if (m < 0 || n < 0 || k < 0 || entry_bits < 1 || entry_bits > 62) return MMP_EINVAL;
     if (nprimes < 1 || !primes || !C) return MMP_EINVAL;
     if (opts) {
-      for (int r : opts->reserved)
-        if (r != 0) return MMP_EINVAL;
+      if (opts->batch_launch != 0) return MMP_EINVAL;
       if (opts->prepared_a || opts->prepared_b) return MMP_EINVAL;
     }
     for (int i = 0; i < nprimes; i++) {

@@ -187,6 +187,10 @@ int launch_crt(int digits, const CrtLaunch& c, void* stream);
 // kMaxBatch products with the same digit count (each with its own planes).
 int launch_int8_digitize(int digits, const Int8Args& a, void* stream);
 int launch_int8_gemm(int digits, const Int8Args* jobs, int njobs, void* stream);
+// Digit planes and digit GEMM of up to 64 whole products (no resident
+// planes, no split-K) of any digit counts: one launch each.
+constexpr int kMaxMixedBatch = 64;
+int launch_int8_batch(const Int8Args* jobs, const int* digits, int njobs, void* stream);
 
 // Phase timer hooks (null tokens unless mmp_timers_enable(1)).  A launch
 // passes timer_start(t) / timer_stop(t) as the start and stop events of

@@ -545,8 +545,7 @@ static int plan_impl(uint64_t p, int u, int v, int64_t m, int64_t n, int64_t k, 
   std::memset(&o, 0, sizeof(o));
   if (opts) o = *opts;
   if (opts) {
-    for (int r : opts->reserved)
-      if (r != 0) return MMP_EINVAL;
+    if (opts->batch_launch < 0 || opts->batch_launch > 2) return MMP_EINVAL;
     // prepared operands are taken by mm_modp_async alone, which plans without them
     if (opts->prepared_a || opts->prepared_b) return MMP_EINVAL;
   }

@@ -300,3 +300,108 @@ def test_graph_capture_reconstruction_and_prepared_product_replays():
         x = torch.randn(1000, device="cuda").sum()
         torch.cuda.synchronize()
         del x
+
+
+def _mix64(seed, count=64, dim_hi=700):
+    """Products with bitsizes uniform in 20..52 (every digit count 3..7) and
+    log-uniform dimensions: the serving mix at test size."""
+    reqs = gen.serve_stream(count, 1.0, seed=seed, dim_lo=16, dim_hi=dim_hi)
+    out = []
+    for r in reqs:
+        pr = r.problem
+        A, B = pr.a(), pr.b()
+        out.append((pr, A, B, dev(A), dev(B), torch.full((pr.m, pr.n), -1.0, dtype=torch.float64, device="cuda")))
+    return out
+
+
+def test_one_launch_batch_of_mixed_digit_counts():
+    items = _mix64(91)
+    digits = sorted({(pr.p.bit_length() + 7) // 8 for pr, *_ in items})
+    say("mixed batch digit counts", digits, "bits", sorted({pr.p.bit_length() for pr, *_ in items}))
+    assert len(digits) >= 4
+    jobs = [(dA, dB, C, pr.p, 0, 0) for pr, A, B, dA, dB, C in items]
+    torch.cuda.synchronize()
+    mmp.timers_read(reset=True)
+    mmp.timers_enable(True)
+    mmp.mm_modp_batched(jobs, form=mmp.FORM_INT8_WORDS)
+    torch.cuda.synchronize()
+    mmp.timers_enable(False)
+    t = mmp.timers_read(reset=True)
+    say("timers", t)
+    # the planes of all 64 products in one launch, their GEMM in one more
+    assert t == {"int8_batch_digitize": (1, t["int8_batch_digitize"][1]), "int8_batch_gemm": (1, t["int8_batch_gemm"][1])}
+    grouped = [torch.full_like(C, -2.0) for *_, C in items]
+    mmp.mm_modp_batched([(dA, dB, G, pr.p, 0, 0) for (pr, A, B, dA, dB, C), G in zip(items, grouped)],
+                        form=mmp.FORM_INT8_WORDS, batch_launch=1)
+    torch.cuda.synchronize()
+    for (pr, A, B, dA, dB, C), G in zip(items, grouped):
+        want = oracle.mm_modp(pr.p, A, B).astype(np.float64)
+        assert np.array_equal(C.cpu().numpy(), want), (pr.m, pr.n, pr.k, pr.p)
+        assert torch.equal(C, G)
+
+
+def test_one_launch_batch_more_than_64_and_ragged():
+    # 70 products: two launches of each kernel; a k = 0 product is zero-filled
+    items = _mix64(92, count=70, dim_hi=200)
+    jobs = [(dA, dB, C, pr.p, 0, 0) for pr, A, B, dA, dB, C in items]
+    z = torch.full((3, 4), 5.0, dtype=torch.float64, device="cuda")
+    jobs.append((torch.zeros((3, 0), dtype=torch.float64, device="cuda"),
+                 torch.zeros((0, 4), dtype=torch.float64, device="cuda"), z, 65521, 0, 0))
+    mmp.timers_read(reset=True)
+    mmp.timers_enable(True)
+    mmp.mm_modp_batched(jobs, form=mmp.FORM_INT8_WORDS, batch_launch=2)
+    torch.cuda.synchronize()
+    mmp.timers_enable(False)
+    t = mmp.timers_read(reset=True)
+    assert t["int8_batch_digitize"][0] == 2 and t["int8_batch_gemm"][0] == 2
+    for pr, A, B, dA, dB, C in items:
+        assert np.array_equal(C.cpu().numpy(), oracle.mm_modp(pr.p, A, B).astype(np.float64))
+    assert torch.all(z == 0)
+
+
+def _replay_check(work, outs, wants, reps=3):
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        work(s)  # warm-up outside the graph
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        work(s)
+    for rep in range(reps):
+        for C in outs:
+            C.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for C, w in zip(outs, wants):
+            assert np.array_equal(C.cpu().numpy(), w), rep
+        x = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        del x
+
+
+def test_graph_capture_one_launch_batch_replays():
+    items = _mix64(93, count=24, dim_hi=300)
+    jobs = [(dA, dB, C, pr.p, 0, 0) for pr, A, B, dA, dB, C in items]
+    ws = torch.empty(max(mmp.workspace_batched(jobs, form=mmp.FORM_INT8_WORDS), 1), dtype=torch.uint8,
+                     device="cuda")
+    wants = [oracle.mm_modp(pr.p, A, B).astype(np.float64) for pr, A, B, *_ in items]
+    _replay_check(lambda s: mmp.mm_modp_batched(jobs, stream=s, workspace=ws, form=mmp.FORM_INT8_WORDS),
+                  [C for *_, C in items], wants)
+
+
+def test_graph_capture_fp64_word_batch_replays():
+    # FP64-word products of several word pairs and blocks: no workspace
+    cases = [(33554393, 1, 1), (8388593, 1, 2), (1125899906842597, 2, 2), (68719476731, 1, 3),
+             (4503599627370449, 2, 3), (1099511627689, 2, 2)]
+    items = []
+    for i, (p, u, v) in enumerate(cases):
+        m, n, k = 40 + 17 * i, 33 + 5 * i, 100 + 61 * i
+        A = gen.random_matrix(100 + i, 1, m, k, p)
+        B = gen.random_matrix(100 + i, 2, k, n, p)
+        items.append((p, u, v, A, B, dev(A), dev(B), torch.zeros((m, n), dtype=torch.float64, device="cuda")))
+    jobs = [(dA, dB, C, p, u, v) for p, u, v, A, B, dA, dB, C in items]
+    assert mmp.workspace_batched(jobs) == 0
+    wants = [oracle.mm_modp(p, A, B).astype(np.float64) for p, u, v, A, B, *_ in items]
+    _replay_check(lambda s: mmp.mm_modp_batched(jobs, stream=s), [C for *_, C in items], wants)

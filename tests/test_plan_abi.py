@@ -187,11 +187,18 @@ def test_forced_block_estimate_matches_the_planner_s_own():
             assert forced[key] == pytest.approx(auto[key]), (p, key)
 
 
-def test_reserved_options_rejected():
+def test_batch_launch_option_range():
     o = mmp.MmpOpts()
-    o.reserved[0] = 1
     out = mmp.MmpPlan()
-    assert mmp.lib().mmp_plan(33554393, 1, 1, 8, 8, 8, ctypes.byref(o), ctypes.byref(out)) == -1
+    for bad in (-1, 3):
+        o.batch_launch = bad
+        assert mmp.lib().mmp_plan(33554393, 1, 1, 8, 8, 8, ctypes.byref(o), ctypes.byref(out)) == -1
+    o.batch_launch = 2
+    assert mmp.lib().mmp_plan(33554393, 1, 1, 8, 8, 8, ctypes.byref(o), ctypes.byref(out)) == 0
+    # a batch option: single products refuse it before any device work
+    fake = ctypes.c_void_p(0x10000)
+    assert mmp.lib().mm_modp_async(ctypes.byref(o), 33554393, 0, 0, 8, 8, 8, fake, 8, ctypes.c_void_p(0x20000000),
+                                   8, ctypes.c_void_p(0x40000000), 8, None) == -1
 
 
 def test_footprint_counts_word_copies():
