@@ -330,6 +330,41 @@ def bench_crt(args, mmp, torch, gen):
         "reconstruction": rec, "product_counts": counts}), flush=True)
 
 
+def bench_autotune(args, mmp, torch, gen):
+    """The eight skinny workloads (16384^2 x 256 and 512^2 x 131072 at 23, 31,
+    40 and 52 bits) through the autotuner: per workload the tuned choice
+    (form, words, tile, block) and its time per call against the planner's
+    default plan, with outputs checked identical.  One JSON line per workload."""
+    for prob in gen.config_problems(4):
+        mmp.tune_cache_clear()
+        default = mmp.plan(prob.p, prob.m, prob.n, prob.k)
+        dA = torch.from_numpy(prob.a().astype("float64")).cuda()
+        dB = torch.from_numpy(prob.b().astype("float64")).cuda()
+        C0 = torch.empty((prob.m, prob.n), dtype=torch.float64, device="cuda")
+        C1 = torch.empty_like(C0)
+        t_default = _time(torch, lambda: mmp.mm_modp_async(dA, dB, C0, prob.p), 2, args.steps)
+        t0 = time.perf_counter()
+        best, tried = mmp.autotune(prob.p, prob.m, prob.n, prob.k)
+        tune_s = time.perf_counter() - t0
+        tuned = mmp.plan(prob.p, prob.m, prob.n, prob.k)  # AUTO follows the cache now
+        t_tuned = _time(torch, lambda: mmp.mm_modp_async(dA, dB, C1, prob.p), 2, args.steps)
+        torch.cuda.synchronize()
+
+        def desc(pl):
+            if pl["form"] == 2:
+                return {"form": "int8_digits", "digits": pl["digits_a"], "splits": pl["splits"]}
+            return {"form": "fp64_words", "uv": [pl["u"], pl["v"]], "tile": pl["tile"], "kblock": pl["kblock"],
+                    "slots": pl["slots"], "splits": pl["splits"]}
+        print(json.dumps({"workload": prob.tag, "shape": [prob.m, prob.n, prob.k], "p": prob.p,
+                          "bits": prob.p.bit_length(), "candidates_timed": tried, "tune_s": round(tune_s, 2),
+                          "default": desc(default), "default_ms": round(t_default, 4),
+                          "tuned": desc(tuned), "tuned_ms": round(t_tuned, 4),
+                          "identical": bool(torch.equal(C0, C1))}), flush=True)
+        del dA, dB, C0, C1
+        torch.cuda.empty_cache()
+    mmp.tune_cache_clear()
+
+
 def sweep_bits(args, mmp, torch, gen):
     """Both word forms on one shape for each bitsize: which one wins."""
     import numpy as np
@@ -517,6 +552,8 @@ def main():
                     help="requests in the serving measurement (0: skip it)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="comma-separated fractions of the measured capacity to offer")
+    ap.add_argument("--autotune", action="store_true",
+                    help="the eight skinny workloads through the autotuner, against the planner's default")
     ap.add_argument("--crt", action="store_true",
                     help="time the multi-modular job (2048^3 integers < 2^60 against 32 primes) instead")
     ap.add_argument("--sweep-bits", default="",
@@ -564,6 +601,8 @@ def main():
 
     if args.crt:
         return bench_crt(args, mmp, torch, gen)
+    if args.autotune:
+        return bench_autotune(args, mmp, torch, gen)
     if args.sweep_bits:
         return sweep_bits(args, mmp, torch, gen)
     if args.unbalanced:
