@@ -418,7 +418,10 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
         // Nudge the machine schedule toward that order: the fragment reads,
         // then a reduction's VALU operations between MFMAs (left alone, the
         // compiler gathers the MFMAs into bursts; hard scheduling fences
-        // enforcing the exact order measured slower).
+        // enforcing the exact order measured slower).  Only for correction-
+        // free blocks of 8 slots (the paper's bound at 45-50 bits and the
+        // like), where it measured faster: the grouping costs compile time.
+        if constexpr (LAZY && FE == 2) {
         __builtin_amdgcn_sched_group_barrier(0x100, U * TM + V * TN, 0);  // LDS reads
         if (ks % FE == 0) {
           __builtin_amdgcn_sched_group_barrier(0x002, 2 * kRedOps, 0);
@@ -430,6 +433,7 @@ __global__ __launch_bounds__(kThreads, 2) void fp64_words_kernel(const Fp64Batch
           __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         } else {
           __builtin_amdgcn_sched_group_barrier(0x008, NACC, 0);
+        }
         }
       }
       if (s + 1 < s_end) {
