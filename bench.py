@@ -552,6 +552,8 @@ def main():
                     help="requests in the serving measurement (0: skip it)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="comma-separated fractions of the measured capacity to offer")
+    ap.add_argument("--batch-mix", action="store_true",
+                    help="only the 64-product batch of mixed digit counts, one-launch and grouped forms")
     ap.add_argument("--autotune", action="store_true",
                     help="the eight skinny workloads through the autotuner, against the planner's default")
     ap.add_argument("--crt", action="store_true",
@@ -603,6 +605,9 @@ def main():
         return bench_crt(args, mmp, torch, gen)
     if args.autotune:
         return bench_autotune(args, mmp, torch, gen)
+    if args.batch_mix:
+        print(json.dumps(batched_mix(mmp, torch, gen, max(3, min(args.steps, 10)))), flush=True)
+        return
     if args.sweep_bits:
         return sweep_bits(args, mmp, torch, gen)
     if args.unbalanced:

@@ -7,11 +7,12 @@
 //   - digitize_batch_kernel: the workgroups of every product's row part (A)
 //     and column part (B) one after another; each workgroup finds its product
 //     and runs that product's digit count's code (a uniform branch).
-//   - int8_batch_gemm_kernel: a persistent grid over the (product, 64 x 32
+//   - int8_batch_gemm_kernel: a persistent grid over the (product, output
 //     tile) work items of all products; a workgroup strides over the items
 //     and runs each with its product's digit count.  Every digit count uses
-//     4 waves of 16 x 32 output tiles, so one launch shape serves all; the
-//     LDS ring is sized for the largest digit count of the launch.
+//     4 waves (64 x 64 tiles up to 4 digits, 64 x 32 beyond), so one launch
+//     shape serves all; the LDS ring is sized for the largest digit count of
+//     the launch.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -96,70 +97,85 @@ __global__ __launch_bounds__(256) void digitize_batch_kernel(const MixedBatch b)
   }
 }
 
-// 4 waves stacked along m, each 16 rows x 32 columns (two 16 x 16 tiles) for
-// every digit count; two-stage ring.
+// 4 waves for every digit count: 64 x 64 tiles of 32 x 32 wave tiles up to
+// 4 digits (the digit GEMM's own shape there), 64 x 32 tiles of 16 x 32 wave
+// tiles beyond (with every digit count's code in one kernel, the 5-digit
+// 32 x 32 accumulators spill); two-stage ring.
 template <int D>
 struct MixedShape {
-  static constexpr int WM = 4, WN = 1, TM = 1, TN = 2;
-  static constexpr int BM = 64, BN = 32;
+  static constexpr bool WIDE = D <= 4;
+  static constexpr int WM = WIDE ? 2 : 4, WN = WIDE ? 2 : 1, TM = WIDE ? 2 : 1, TN = 2;
+  static constexpr int BM = 64, BN = WIDE ? 64 : 32;
   static constexpr int THREADS = 256;
   static constexpr int STAGES = 2;
 };
 
-constexpr int64_t mixed_ring_bytes(int D) { return (int64_t)2 * D * (64 + 32) * 64; }
+constexpr int64_t mixed_ring_bytes(int D) { return (int64_t)2 * D * (64 + (D <= 4 ? 64 : 32)) * 64; }
+constexpr int mixed_bn(int D) { return D <= 4 ? 64 : 32; }
 
-// One 64 x 32 output tile of product a: the digit loop over its whole k,
-// folds into binary64 residues, one store.
+// One output tile of product a: the digit loop over its whole k, folds into
+// binary64 residues, one store.
 template <int D>
 __device__ __forceinline__ void gemm_item(const MixedJob& a, int local, int8_t* lds) {
   using S = MixedShape<D>;
   constexpr int ND = 2 * D - 1;
-  constexpr int BM = S::BM, BN = S::BN, TN = S::TN;
+  constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
   auto& sm = *reinterpret_cast<DigitRing<D, BM, BN, S::STAGES>*>(lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave * 16;
+  const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
   int tmi, tni;
   tile_coords(local, nbm * nbn, nbm, nbn, tmi, tni);
   const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
 
-  int4v acc[ND][1][TN];
+  int4v acc[ND][TM][TN];
 #pragma unroll
   for (int s = 0; s < ND; s++)
 #pragma unroll
-    for (int y = 0; y < TN; y++) acc[s][0][y] = (int4v){0, 0, 0, 0};
-  double F[TN][4];
+    for (int x = 0; x < TM; x++)
 #pragma unroll
-  for (int y = 0; y < TN; y++)
+      for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
+  double F[TM][TN][4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) F[y][r] = 0.0;
-  const double p = a.p, q = a.q;
-  auto fold = [&]() {
+  for (int x = 0; x < TM; x++)
 #pragma unroll
     for (int y = 0; y < TN; y++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        int w[ND];
+      for (int r = 0; r < 4; r++) F[x][y][r] = 0.0;
+  const double p = a.p, q = a.q;
+  auto fold = [&]() {
 #pragma unroll
-        for (int s = 0; s < ND; s++) w[s] = acc[s][0][y][r];
-        F[y][r] = addmod(F[y][r], fold_weights<ND>(w, p, q), p);
-      }
+    for (int x = 0; x < TM; x++)
+#pragma unroll
+      for (int y = 0; y < TN; y++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          int w[ND];
+#pragma unroll
+          for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
+          F[x][y][r] = addmod(F[x][y][r], fold_weights<ND>(w, p, q), p);
+        }
 #pragma unroll
     for (int s = 0; s < ND; s++)
 #pragma unroll
-      for (int y = 0; y < TN; y++) acc[s][0][y] = (int4v){0, 0, 0, 0};
+      for (int x = 0; x < TM; x++)
+#pragma unroll
+        for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
   };
   digit_tile_loop<D, S>(a.Ad, a.Bd, a.m, a.n, a.kp, m0, n0, 0, a.kp / kBK8, a.stages_per_block, sm, acc, fold);
+  // 16x16x64 INT8 MFMA output layout: value (i & 3) of lane j + 16 (i >> 2)
   const int lrow = lane & 15;
 #pragma unroll
-  for (int y = 0; y < TN; y++) {
-    const int64_t col = n0 + y * 16 + lrow;
+  for (int x = 0; x < TM; x++)
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const int64_t row = m0 + wm + (lane >> 4) * 4 + r;
-      if (row < a.m && col < a.n) a.C[row * a.ldc + col] = F[y][r] + 0.0;
+    for (int y = 0; y < TN; y++) {
+      const int64_t col = n0 + wn + y * 16 + lrow;
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
+        if (row < a.m && col < a.n) a.C[row * a.ldc + col] = F[x][y][r] + 0.0;
+      }
     }
-  }
 }
 
 __global__ __launch_bounds__(256, 2) void int8_batch_gemm_kernel(const MixedBatch b) {

@@ -16,7 +16,6 @@ int launch_int8_batch(const Int8Args* jobs, const int* digits, int njobs, void* 
   MixedBatch b;
   std::memset(&b, 0, sizeof(b));
   int64_t dig = 0, tiles = 0;
-  int dmax = 1;
   int n = 0;
   for (int j = 0; j < njobs; j++) {
     const Int8Args& g = jobs[j];
@@ -52,9 +51,8 @@ int launch_int8_batch(const Int8Args* jobs, const int* digits, int njobs, void* 
     a.dig_cols = (int)(dig + gx * gy);
     dig += gx * gy + (g.kp / 64) * ((g.n + 63) / 64);
     a.tile_start = (int)tiles;
-    tiles += ((g.m + 63) / 64) * ((g.n + 31) / 32);
+    tiles += ((g.m + 63) / 64) * ((g.n + mixed_bn(D) - 1) / mixed_bn(D));
     if (dig > 0x7fffffff || tiles > 0x7fffffff) return (int)hipErrorInvalidValue;
-    dmax = std::max(dmax, D);
   }
   b.njobs = n;
   b.dig_total = (int)dig;
@@ -70,14 +68,16 @@ int launch_int8_batch(const Int8Args* jobs, const int* digits, int njobs, void* 
   }
   // the ring of the largest digit count, in dynamic LDS; a persistent grid of
   // as many workgroups as the device holds at once with that ring
-  const size_t lds = (size_t)mixed_ring_bytes(dmax);
+  size_t lds = 0;  // the largest ring among the launch's digit counts
+  for (int j = 0; j < n; j++) lds = std::max(lds, (size_t)mixed_ring_bytes(b.job[j].D));
   int dev = 0;
   if (int e = (int)hipGetDevice(&dev)) return e;
   static std::atomic<int> lds_ready[64];
   if (dev < 64 && !lds_ready[dev].load()) {
+    int most = 0;
+    for (int d = 1; d <= kMaxDigits; d++) most = std::max(most, (int)mixed_ring_bytes(d));
     if (int e = (int)hipFuncSetAttribute((const void*)int8_batch_gemm_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)mixed_ring_bytes(kMaxDigits)))
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, most))
       return e;
     lds_ready[dev].store(1);
   }
