@@ -809,9 +809,10 @@ def _fold_direct(w, p, gmax):
         assert abs(d) < p
         t = d + g[j]
         assert abs(t) <= p + gmax and abs(t) < 2 ** 53
-    c = math.floor(float(t) * q)
-    d = t - c * p
-    d = d - p if d >= p else d
+    # the closing rounded reduction, then p added to a negative result
+    assert abs(float(t) / p) <= 2 ** 27
+    d = _reduce_near(float(t), p, q)
+    assert abs(d) <= p / 2 + 1
     d = d + p if d < 0 else d
     assert 0 <= d < p
     return d
