@@ -13,6 +13,8 @@
 // once, at its end, straight into C; from three digits on (p >= 2^16) with
 // fold_short, which the tiles' short k (at most 1024 terms) allows.
 #pragma once
+#include <type_traits>
+
 #include "int8_fold.h"
 
 namespace mmp {
@@ -27,71 +29,69 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
   constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
   constexpr int NW = S::WM * S::WN;
   constexpr int GROUPS = D * (BM + BN) / 16;  // 1 KB copy instructions per stage
-  constexpr int IPW = (GROUPS + NW - 1) / NW;   // per wave; the last ones may idle
+  constexpr int IPW = GROUPS / NW;             // per wave
+  // the first half of the waves copies A's blocks, the second half B's
+  static_assert(GROUPS % NW == 0 && D * BM / 16 == (NW / 2) * IPW && D * BN / 16 == (NW / 2) * IPW,
+                "copies split evenly between A's and B's waves");
   __shared__ __attribute__((aligned(1024))) DigitRing<D, BM, BN, 2> sm;
+  constexpr uint32_t STAGE_BYTES = sizeof(sm.s[0]);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / S::WN) * TM * 16, wn = (wave % S::WN) * TN * 16;
   const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const bool copies_a = wv < NW / 2;
   const int nbm = (int)((a.m + BM - 1) / BM), nbn = (int)((a.n + BN - 1) / BN);
   const int total = nbm * nbn;
   const int G = (int)gridDim.x;
   // stages per tile: at least one, and within one int32 block (launcher)
   const int nst = (int)(a.kp / kBK8);
-  const int64_t planeA = plane_size(a.m, a.kp), planeB = plane_size(a.n, a.kp);
   const int rl = lane >> 2;                                       // row within a 16-row group
   const int ql = (lane & 3) ^ (((lane >> 4) ^ (lane >> 3)) & 3);  // chunk this lane copies
 
-  // Copy offsets of the tile whose stages are being issued: one 1 KB block
-  // of a plane per copy, rows past m or n clamped to the last row.  The same
+  // This wave's copies: block c = (wave mod NW/2) IPW + e of its operand,
+  // digit plane c / (rows / 16), 16-row part c mod (rows / 16).  Each copy
+  // moves one 1 KB block of a plane; the lane offsets (voff, from the
+  // operand's first plane: all its planes lie below 4 GB, launcher) hold
+  // the plane and the tile's rows, rows past m or n clamped to the last
+  // row, so a stage's copies add only the stage's 1 KB step.  The same
   // copies as digit_tile_loop's, written out again here: routing both
   // through one shared helper changed the code the compiler generates for
   // the main digit GEMM (a longer loop), which this form must not touch.
-  uint32_t voff[IPW];  // planes below 4 GB (launcher)
+  const int8_t* const opbase = copies_a ? a.Ad : a.Bd;
+  const int64_t oprows = copies_a ? a.m : a.n;
+  const int64_t opplane = plane_size(oprows, a.kp);
+  constexpr int PARTS = BM / 16;  // == BN / 16
+  static_assert(BM == BN, "square tiles: one part count for both operands");
+  const int c0 = (copies_a ? wv : wv - NW / 2) * IPW;
+  uint32_t lds_off[IPW];  // each copy's row block in stage 0 of the ring
+#pragma unroll
+  for (int e = 0; e < IPW; e++) {
+    const int c = c0 + e, plane = c / PARTS, part = c % PARTS;
+    lds_off[e] = (uint32_t)((plane * (BM + BN) + (copies_a ? 0 : BM) + 16 * part) * 64);
+  }
+  uint32_t voff[IPW];
   auto set_offsets = [&](int64_t m0, int64_t n0) {
+    const int64_t r0 = copies_a ? m0 : n0;
 #pragma unroll
     for (int e = 0; e < IPW; e++) {
-      const int t = wv + NW * e;
-      if (GROUPS % NW != 0 && t >= GROUPS) {
-        voff[e] = 0;  // no copy
-      } else if (t < D * BM / 16) {
-        const int64_t row = m0 + 16 * (t % (BM / 16)) + rl;
-        voff[e] = (uint32_t)plane_at(row < a.m ? row : a.m - 1, 16 * ql, a.kp);
-      } else {
-        const int64_t row = n0 + 16 * ((t - D * BM / 16) % (BN / 16)) + rl;
-        voff[e] = (uint32_t)plane_at(row < a.n ? row : a.n - 1, 16 * ql, a.kp);
-      }
+      const int c = c0 + e, plane = c / PARTS, part = c % PARTS;
+      const int64_t row = r0 + 16 * part + rl;
+      voff[e] = (uint32_t)(plane * opplane + plane_at(row < oprows ? row : oprows - 1, 16 * ql, a.kp));
     }
   };
   auto issue = [&](int st, int b) {
+    const int8_t* const base = opbase + (uint32_t)st * 1024u;
+    const uint32_t ring = (uint32_t)b * STAGE_BYTES;
 #pragma unroll
-    for (int e = 0; e < IPW; e++) {
-      const int t = wv + NW * e;
-      if (GROUPS % NW != 0 && t >= GROUPS) continue;  // uniform per wave
-      const int8_t* base;
-      int plane, row0;
-      if (t < D * BM / 16) {
-        plane = t / (BM / 16);
-        row0 = 16 * (t % (BM / 16));
-        base = a.Ad + plane * planeA + (uint32_t)st * 1024u;
-      } else {
-        const int t2 = t - D * BM / 16;
-        plane = t2 / (BN / 16);
-        row0 = BM + 16 * (t2 % (BN / 16));
-        base = a.Bd + plane * planeB + (uint32_t)st * 1024u;
-      }
-      __builtin_amdgcn_global_load_lds((const void*)(base + voff[e]),
-                                       (__attribute__((address_space(3))) void*)&sm.s[b][plane][row0][0], 16, 0, 0);
-    }
+    for (int e = 0; e < IPW; e++)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(base + voff[e]),
+          (__attribute__((address_space(3))) void*)((__attribute__((address_space(3))) int8_t*)&sm.s[0][0][0][0] +
+                                                    ring + lds_off[e]),
+          16, 0, 0);
   };
 
-  int4v acc[ND][TM][TN];
-#pragma unroll
-  for (int s = 0; s < ND; s++)
-#pragma unroll
-    for (int x = 0; x < TM; x++)
-#pragma unroll
-      for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
+  int4v acc[ND][TM][TN];  // each tile's first stage sets them
   const double p = a.p, q = a.q;
 
   // one tile per outer iteration; the last stage of a tile issues the first
@@ -133,51 +133,83 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
           const int r = BM + wn + y * 16 + lrow;
           bf[j][y] = *(const int4v*)(&sm.s[b][j][r][swz(r, lq)]);
         }
+      // A tile's first stage starts every digit weight from zero: the first
+      // product of each weight (i = max(0, s - D + 1)) takes a zero
+      // accumulator operand, so no instruction clears the accumulators
+      // between tiles.
+      auto mma = [&](auto firstc) {
+        constexpr bool FIRST = decltype(firstc)::value;
 #pragma unroll
-      for (int i = 0; i < D; i++) {
-        int4v af[TM];
+        for (int i = 0; i < D; i++) {
+          int4v af[TM];
 #pragma unroll
-        for (int x = 0; x < TM; x++) {
-          const int r = wm + x * 16 + lrow;
-          af[x] = *(const int4v*)(&sm.s[b][i][r][swz(r, lq)]);
+          for (int x = 0; x < TM; x++) {
+            const int r = wm + x * 16 + lrow;
+            af[x] = *(const int4v*)(&sm.s[b][i][r][swz(r, lq)]);
+          }
+#pragma unroll
+          for (int j = 0; j < D; j++)
+#pragma unroll
+            for (int x = 0; x < TM; x++)
+#pragma unroll
+              for (int y = 0; y < TN; y++) {
+                const bool fresh = FIRST && i == (i + j > D - 1 ? i + j - (D - 1) : 0);
+                acc[i + j][x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                    af[x], bf[j][y], fresh ? (int4v){0, 0, 0, 0} : acc[i + j][x][y], 0, 0, 0);
+              }
         }
-#pragma unroll
-        for (int j = 0; j < D; j++)
-#pragma unroll
-          for (int x = 0; x < TM; x++)
-#pragma unroll
-            for (int y = 0; y < TN; y++)
-              acc[i + j][x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[x], bf[j][y], acc[i + j][x][y], 0, 0, 0);
-      }
+      };
+      if (st == 0)
+        mma(std::true_type{});
+      else
+        mma(std::false_type{});
       b ^= 1;
     }
-    // fold the tile's digit-weight sums into C and clear them; 16x16x64
-    // INT8 MFMA output layout: value (i & 3) of lane j + 16 (i >> 2)
+    // fold the tile's digit-weight sums into C; 16x16x64 INT8 MFMA output
+    // layout: value (i & 3) of lane j + 16 (i >> 2)
+    auto fold_at = [&](int x, int y, int r) {
+      int w[ND];
 #pragma unroll
-    for (int x = 0; x < TM; x++)
-#pragma unroll
-      for (int y = 0; y < TN; y++) {
-        const int64_t col = (int64_t)tni * BN + wn + y * 16 + lrow;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-          int w[ND];
-#pragma unroll
-          for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
-          double t;
-          if constexpr (D >= 3)
-            t = fold_short<ND>(w, p, q);
-          else
-            t = fold_weights<ND>(w, p, q);
-          const int64_t row = (int64_t)tmi * BM + wm + x * 16 + (lane >> 4) * 4 + r;
-          if (row < a.m && col < a.n) a.C[row * a.ldc + col] = t + 0.0;
-        }
-      }
-#pragma unroll
-    for (int s = 0; s < ND; s++)
+      for (int s = 0; s < ND; s++) w[s] = acc[s][x][y][r];
+      if constexpr (D >= 3)
+        return fold_short<ND>(w, p, q);
+      else
+        return fold_weights<ND>(w, p, q);
+    };
+    const int64_t row0 = (int64_t)tmi * BM + wm + (lane >> 4) * 4, col0 = (int64_t)tni * BN + wn + lrow;
+    if ((int64_t)(tmi + 1) * BM <= a.m && (int64_t)(tni + 1) * BN <= a.n) {
+      // whole tile inside C (uniform): no per-element bounds, one row
+      // pointer per output row and the column steps as immediate offsets
+      double* const c0 = a.C + row0 * a.ldc + col0;
 #pragma unroll
       for (int x = 0; x < TM; x++)
 #pragma unroll
-        for (int y = 0; y < TN; y++) acc[s][x][y] = (int4v){0, 0, 0, 0};
+        for (int r = 0; r < 4; r++) {
+          double* const cr = c0 + (int64_t)(x * 16 + r) * a.ldc;
+#pragma unroll
+          for (int y = 0; y < TN; y++) {
+            // fold_short never returns -0: (double) of an int and an exact
+            // fma or sum that is zero give +0 unless both terms are -0
+            if constexpr (D >= 3)
+              cr[y * 16] = fold_at(x, y, r);
+            else
+              cr[y * 16] = fold_at(x, y, r) + 0.0;
+          }
+        }
+    } else {
+#pragma unroll
+      for (int x = 0; x < TM; x++)
+#pragma unroll
+        for (int y = 0; y < TN; y++) {
+          const int64_t col = col0 + y * 16;
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int64_t row = row0 + x * 16 + r;
+            const double t = fold_at(x, y, r);
+            if (row < a.m && col < a.n) a.C[row * a.ldc + col] = t + 0.0;
+          }
+        }
+    }
     if (next >= total) break;  // uniform; nothing was issued past this tile
     item = next;
     tile_coords(item, total, nbm, nbn, tmi, tni);

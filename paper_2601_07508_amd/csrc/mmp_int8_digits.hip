@@ -170,9 +170,10 @@ int64_t persistent_slots() {
 
 // One product of 64 x 64 tiles whose tiles are short (at most
 // kPersistentMaxStages k-stages, whole k per tile, within one int32 block),
-// at least twice as many as the device holds workgroups, and planes below
-// 4 GB (the kernel keeps 32-bit copy offsets): the persistent kernel, one
-// workgroup per resident slot.
+// at least twice as many as the device holds workgroups, and each operand's
+// planes below 4 GB in all (the kernel keeps 32-bit copy offsets from an
+// operand's first plane): the persistent kernel, one workgroup per resident
+// slot.
 constexpr int64_t kPersistentMaxStages = 16;
 int launch_persistent_if_short(const Int8Args& g, hipStream_t s, bool* launched) {
   using namespace i8d;
@@ -180,7 +181,7 @@ int launch_persistent_if_short(const Int8Args& g, hipStream_t s, bool* launched)
   using S = I8Shape<D, false>;
   *launched = false;
   if (g.splits > 1 || g.kp <= 0 || g.kp / kBK8 > kPersistentMaxStages || g.kp > g.kblock) return 0;
-  if (digit_planes_bytes(1, std::max(g.m, g.n), g.kp) >= ((size_t)1 << 32)) return 0;
+  if (digit_planes_bytes(D, std::max(g.m, g.n), g.kp) >= ((size_t)1 << 32)) return 0;
   const int64_t tiles = ((g.m + S::BM - 1) / S::BM) * ((g.n + S::BN - 1) / S::BN);
   const int64_t slots = persistent_slots<D>();
   if (tiles < 2 * slots || tiles > 0x7fffffff) return 0;
