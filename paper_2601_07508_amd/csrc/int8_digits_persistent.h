@@ -104,34 +104,53 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
   issue(0, 0);
   int b = 0;
   const int lrow = lane & 15, lq = lane >> 4;
+  // Store instructions the whole-tile epilogue issues (one per output
+  // element: a lane's elements are never adjacent, so none merge).  Vector
+  // memory instructions complete in issue order for the vmcnt counter, so
+  // after that epilogue the next tile's first stage, whose copies were
+  // issued before those stores, waits only until that many remain.
+  constexpr int NSTORES = TM * TN * 4;
+  bool stores_behind = false;
+  int nti = 0, ntj = 0;  // the next tile's coordinates
   for (;;) {
     const int next = item + G;
     for (int st = 0; st < nst; st++) {
       // this wave's copies of stage st are complete; the barrier extends
       // that to every wave and ends the reads of the previous stage, whose
       // buffer the next copies overwrite
-      wait_vm<0>();
+      if (st == 0 && stores_behind)
+        wait_vm<NSTORES>();
+      else
+        wait_vm<0>();
       asm volatile("" ::: "memory");
       __builtin_amdgcn_s_barrier();
       asm volatile("" ::: "memory");
       // one issue site: the tile's next stage, or the next tile's first
+      // (whose copy offsets the previous stage set, or this one if it is
+      // the tile's only stage)
       int st_n = st + 1;
       if (st_n == nst) {
         st_n = next < total ? 0 : -1;
-        if (st_n == 0) {
-          int ti, tj;
-          tile_coords(next, total, nbm, nbn, ti, tj);
-          set_offsets((int64_t)ti * BM, (int64_t)tj * BN);
+        if (nst == 1 && st_n == 0) {
+          tile_coords(next, total, nbm, nbn, nti, ntj);
+          set_offsets((int64_t)nti * BM, (int64_t)ntj * BN);
         }
       }
       if (st_n >= 0) issue(st_n, b ^ 1);
-      int4v bf[D][TN];
+      int4v bf[D][TN], af[D][TM];
 #pragma unroll
       for (int j = 0; j < D; j++)
 #pragma unroll
         for (int y = 0; y < TN; y++) {
           const int r = BM + wn + y * 16 + lrow;
           bf[j][y] = *(const int4v*)(&sm.s[b][j][r][swz(r, lq)]);
+        }
+#pragma unroll
+      for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int x = 0; x < TM; x++) {
+          const int r = wm + x * 16 + lrow;
+          af[i][x] = *(const int4v*)(&sm.s[b][i][r][swz(r, lq)]);
         }
       // A tile's first stage starts every digit weight from zero: the first
       // product of each weight (i = max(0, s - D + 1)) takes a zero
@@ -141,12 +160,6 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
         constexpr bool FIRST = decltype(firstc)::value;
 #pragma unroll
         for (int i = 0; i < D; i++) {
-          int4v af[TM];
-#pragma unroll
-          for (int x = 0; x < TM; x++) {
-            const int r = wm + x * 16 + lrow;
-            af[x] = *(const int4v*)(&sm.s[b][i][r][swz(r, lq)]);
-          }
 #pragma unroll
           for (int j = 0; j < D; j++)
 #pragma unroll
@@ -155,7 +168,7 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
               for (int y = 0; y < TN; y++) {
                 const bool fresh = FIRST && i == (i + j > D - 1 ? i + j - (D - 1) : 0);
                 acc[i + j][x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                    af[x], bf[j][y], fresh ? (int4v){0, 0, 0, 0} : acc[i + j][x][y], 0, 0, 0);
+                    af[i][x], bf[j][y], fresh ? (int4v){0, 0, 0, 0} : acc[i + j][x][y], 0, 0, 0);
               }
         }
       };
@@ -163,10 +176,18 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
         mma(std::true_type{});
       else
         mma(std::false_type{});
+      // the next tile's copy offsets, once this tile's last copies are
+      // issued, behind this stage's products
+      if (st == nst - 2 && next < total) {
+        tile_coords(next, total, nbm, nbn, nti, ntj);
+        set_offsets((int64_t)nti * BM, (int64_t)ntj * BN);
+      }
       b ^= 1;
     }
     // fold the tile's digit-weight sums into C; 16x16x64 INT8 MFMA output
-    // layout: value (i & 3) of lane j + 16 (i >> 2)
+    // layout: value (i & 3) of lane j + 16 (i >> 2).  C is written once and
+    // not read here again: streaming (nontemporal) stores keep it from
+    // displacing the digit planes the next tiles read from L2.
     auto fold_at = [&](int x, int y, int r) {
       int w[ND];
 #pragma unroll
@@ -177,7 +198,8 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
         return fold_weights<ND>(w, p, q);
     };
     const int64_t row0 = (int64_t)tmi * BM + wm + (lane >> 4) * 4, col0 = (int64_t)tni * BN + wn + lrow;
-    if ((int64_t)(tmi + 1) * BM <= a.m && (int64_t)(tni + 1) * BN <= a.n) {
+    stores_behind = (int64_t)(tmi + 1) * BM <= a.m && (int64_t)(tni + 1) * BN <= a.n;
+    if (stores_behind) {
       // whole tile inside C (uniform): no per-element bounds, one row
       // pointer per output row and the column steps as immediate offsets
       double* const c0 = a.C + row0 * a.ldc + col0;
@@ -191,9 +213,9 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
             // fold_short never returns -0: (double) of an int and an exact
             // fma or sum that is zero give +0 unless both terms are -0
             if constexpr (D >= 3)
-              cr[y * 16] = fold_at(x, y, r);
+              __builtin_nontemporal_store(fold_at(x, y, r), &cr[y * 16]);
             else
-              cr[y * 16] = fold_at(x, y, r) + 0.0;
+              __builtin_nontemporal_store(fold_at(x, y, r) + 0.0, &cr[y * 16]);
           }
         }
     } else {
@@ -206,13 +228,14 @@ int8_digits_gemm_persistent_kernel(const GemmArgs a) {
           for (int r = 0; r < 4; r++) {
             const int64_t row = row0 + x * 16 + r;
             const double t = fold_at(x, y, r);
-            if (row < a.m && col < a.n) a.C[row * a.ldc + col] = t + 0.0;
+            if (row < a.m && col < a.n) __builtin_nontemporal_store(t + 0.0, &a.C[row * a.ldc + col]);
           }
         }
     }
     if (next >= total) break;  // uniform; nothing was issued past this tile
     item = next;
-    tile_coords(item, total, nbm, nbn, tmi, tni);
+    tmi = nti;
+    tni = ntj;
   }
 }
 
