@@ -41,7 +41,9 @@ def log(*a):
 # counter record taken on other sources than these is stale.
 KERNEL_SOURCES = {
     1: ["fp64_words_kernel.h", "mmp_fp64_words.hip"],
-    2: ["int8_digits_kernel.h"],  # the digit GEMM (the digitize passes live in int8_digitize_kernel.h)
+    # the digit GEMM, its persistent form and their folds (the digitize passes
+    # live in int8_digitize_kernel.h)
+    2: ["int8_digits_kernel.h", "int8_digits_persistent.h", "int8_fold.h"],
 }
 
 
@@ -687,9 +689,24 @@ def main():
         form_desc = f"{plan['digits_a']} signed 8-bit digits per entry on INT8 MFMA"
     launches, total_ms = phases.get(phase, (0, 0.0))
     kern_ms = total_ms / max(launches, 1)
-    achieved = work / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
+    # Algorithmic HBM bytes of the dominant kernel: the binary64 operands
+    # read once and C written once (FP64 words), or both operands' digit
+    # planes read once and C written once (INT8 digits).  The roof that
+    # binds is the larger of the two times at peak: MFMA work or bytes.
+    mn, mk, kn = float(prob.m) * prob.n, float(prob.m) * prob.k, float(prob.k) * prob.n
+    if plan["form"] == 1:
+        alg_bytes = 8.0 * (mk + kn + mn)
+    else:
+        alg_bytes = plan["digits_a"] * mk + plan["digits_b"] * kn + 8.0 * mn
+    hbm_bound = alg_bytes / (HBM_PEAK_GBS * 1e9) > work / (peak * 1e12)
+    if hbm_bound:
+        achieved = alg_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+        bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = work / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
+        bound = "mfma"
     roofline = {
-        "bound": "mfma",
+        "bound": bound,
         "achieved": round(achieved, 3),
         "peak": peak,
         "unit": unit,
@@ -698,6 +715,7 @@ def main():
         "kernel": kernel,
         "kernel_ms": round(kern_ms, 4),
         "algorithmic_work_per_launch": work,
+        "algorithmic_bytes_per_launch": alg_bytes,
     }
     shape = "square" if prob.m == prob.n == prob.k else "product"
     fill = ", all entries p - 1" if prob.fill == "pmax" else ""
