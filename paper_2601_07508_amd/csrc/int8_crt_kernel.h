@@ -14,6 +14,7 @@
 // the launcher checks Gmax <= (2^27 - 2) p), else over the groups each
 // reduced first (fold_groups).
 #pragma once
+#include <type_traits>
 #include "int8_fold.h"
 
 namespace mmp {
@@ -71,23 +72,58 @@ __global__ __launch_bounds__(I8Shape<D>::THREADS, I8Shape<D>::GROUPS_PER_CU) voi
         for (int j = 0; j < NG; j++) g[x][y][r][j] = weight_group<ND>(w, j);
       }
 
+  // One pass over the moduli per fold form (a uniform choice).  Each
+  // modulus's C is written once and not read here again: streaming
+  // (nontemporal) stores keep the 32 outputs from displacing the digit
+  // planes other tiles read from L2.  A whole tile inside C (uniform) takes
+  // no per-element bounds and one row pointer per output row.
   const int lrow = lane & 15;
-  for (int pi = 0; pi < a.nprimes; pi++) {
-    const double p = a.p[pi], q = a.q[pi];
-    double* C = a.C[pi];
+  const int64_t row0 = m0 + wm + (lane >> 4) * 4, col0 = n0 + wn + lrow;
+  const bool whole = m0 + BM <= a.m && n0 + BN <= a.n;
+  auto moduli = [&](auto directc) {
+    constexpr bool DIRECT = decltype(directc)::value;
+    for (int pi = 0; pi < a.nprimes; pi++) {
+      const double p = a.p[pi], q = a.q[pi];
+      double* const C = a.C[pi];
+      auto fold = [&](int x, int y, int r) {
+        // fold_direct over weight groups never returns -0 (an int converted
+        // to binary64, or an exact fma or sum that is zero, is +0 unless
+        // both terms are -0); the other form's result is normalised
+        if constexpr (DIRECT)
+          return fold_direct<NG>(g[x][y][r], p, q);
+        else
+          return fold_groups<NG>(g[x][y][r], p, q) + 0.0;
+      };
+      if (whole) {
+        double* const c0 = C + row0 * a.ldc + col0;
 #pragma unroll
-    for (int x = 0; x < TM; x++)
+        for (int x = 0; x < TM; x++)
 #pragma unroll
-      for (int y = 0; y < TN; y++) {
-        const int64_t col = n0 + wn + y * 16 + lrow;
+          for (int r = 0; r < 4; r++) {
+            double* const cr = c0 + (int64_t)(x * 16 + r) * a.ldc;
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-          const double t = a.direct ? fold_direct<NG>(g[x][y][r], p, q) : fold_groups<NG>(g[x][y][r], p, q);
-          const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
-          if (row < a.m && col < a.n) C[row * a.ldc + col] = t + 0.0;
-        }
+            for (int y = 0; y < TN; y++) __builtin_nontemporal_store(fold(x, y, r), &cr[y * 16]);
+          }
+      } else {
+#pragma unroll
+        for (int x = 0; x < TM; x++)
+#pragma unroll
+          for (int y = 0; y < TN; y++) {
+            const int64_t col = col0 + y * 16;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              const double t = fold(x, y, r);
+              const int64_t row = row0 + x * 16 + r;
+              if (row < a.m && col < a.n) __builtin_nontemporal_store(t, &C[row * a.ldc + col]);
+            }
+          }
       }
-  }
+    }
+  };
+  if (a.direct)
+    moduli(std::true_type{});
+  else
+    moduli(std::false_type{});
 }
 
 }  // namespace i8d
