@@ -173,7 +173,7 @@ __device__ __forceinline__ void gemm_item(const MixedJob& a, int local, int8_t* 
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
-        if (row < a.m && col < a.n) a.C[row * a.ldc + col] = F[x][y][r] + 0.0;
+        if (row < a.m && col < a.n) __builtin_nontemporal_store(F[x][y][r] + 0.0, &a.C[row * a.ldc + col]);
       }
     }
 }

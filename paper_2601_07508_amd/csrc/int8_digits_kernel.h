@@ -354,8 +354,8 @@ int8_digits_gemm_kernel(const GemmBatch bt) {
       for (int r = 0; r < 4; r++) {
         const int64_t row = m0 + wm + x * 16 + (lane >> 4) * 4 + r;
         if (row < a.m && col < a.n) {
-          if (a.splits == 1)
-            a.C[row * a.ldc + col] = F[x][y][r] + 0.0;
+          if (a.splits == 1)  // C is written once: a streaming store
+            __builtin_nontemporal_store(F[x][y][r] + 0.0, &a.C[row * a.ldc + col]);
           else
             a.partial[((int64_t)split * a.m + row) * a.n + col] = F[x][y][r];
         }
