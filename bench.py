@@ -180,9 +180,17 @@ def _residues_ok(torch, C, p):
     return bool(torch.all((C >= 0) & (C < p) & (C == torch.floor(C))))
 
 
-def _time(torch, fn, warmup, steps):
-    for _ in range(warmup):
+def _time(torch, fn, warmup, steps, min_warm_s=0.25):
+    """ms per call over `steps` back-to-back calls, after `warmup` calls and
+    at least `min_warm_s` seconds of them: the first tens of milliseconds of
+    a burst of short calls run at a clock the chip does not hold."""
+    t0 = time.perf_counter()
+    done = 0
+    while done < warmup or time.perf_counter() - t0 < min_warm_s:
         fn()
+        done += 1
+        if done % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
