@@ -13,6 +13,7 @@ import pytest
 
 import mmp_inputs as gen
 import oracle
+from tests import freivalds
 
 pytestmark = pytest.mark.gpu
 
@@ -233,8 +234,11 @@ def test_int8_many_short_tiles(p):
     # at most 16 k-stages, more than twice the workgroups the device holds at
     # once: the persistent kernel (one workgroup per resident slot walking
     # its tiles, the copy ring running across tiles); ragged m, n and k, k
-    # of one stage and of exactly 16.  Checked on
-    # sampled rows (every column) against the oracle.
+    # of one stage and of exactly 16.  Checked on sampled rows (every
+    # column) against the oracle, and every entry by Freivalds' check: a
+    # tile's first stage waits only for its own copies after a whole tile's
+    # stores, and edge tiles take the bounded store path, so an ordering
+    # mistake would show in tiles that no sampled row meets.
     rng = np.random.default_rng(11)
     for (m, n, k) in ((4100, 4090, 300), (4160, 4096, 64), (4096, 4111, 1024), (8200, 2060, 17)):
         A = gen.random_matrix(m + k, 1, m, k, p)
@@ -251,6 +255,7 @@ def test_int8_many_short_tiles(p):
         assert t.get("int8_gemm", (0, 0))[0] == 0, t
         assert t.get("int8_digitize", (0, 0))[0] == 1, t  # both operands, one launch
         assert_exact(C[rows], oracle.mm_modp(p, A[rows], B))
+        freivalds.check(p, A, B, C, seed=m + n + k, trials=2 if p > 1000 else 8)
 
 
 @pytest.mark.parametrize("p", [251, 65521, 8388593, 2147483647, 68719476731, 281474976710597, 4503599627370449])
