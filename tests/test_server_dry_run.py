@@ -48,8 +48,11 @@ def test_admission_respects_budget_and_slots():
                         done[t] = r
             time.sleep(1e-4)
         assert len(done) == 6 and all(s == 0 for s, _ in done.values())
-        assert 1 <= peak_running <= 2
+        # the polls may miss every running batch on a loaded host; the
+        # server's own high-water mark sees each launch
+        assert peak_running <= 2
         st = srv.stats()
+        assert 1 <= st["max_running"] <= 2
         assert st["submitted"] == 6 and st["completed"] == 6 and st["rejected"] == 0
         assert st["peak_used_bytes"] <= 2 * fp + fp // 2
         # FIFO: later tickets cannot finish much earlier than earlier ones
