@@ -15,9 +15,18 @@ int launch_int8_batch(const Int8Args* jobs, const int* digits, int njobs, void* 
   hipStream_t s = (hipStream_t)stream;
   MixedBatch b;
   std::memset(&b, 0, sizeof(b));
+  // The grid strides over the work items in table order, so the products
+  // with the costliest tiles (digit products x k x tile width) go first and
+  // the cheap tiles fill in at the end: every workgroup finishes close to
+  // the others.
+  int order[kMaxMixedJobs];
+  for (int j = 0; j < njobs; j++) order[j] = j;
+  auto tile_cost = [&](int j) { return (int64_t)digits[j] * digits[j] * jobs[j].kp * mixed_bn(digits[j]); };
+  std::stable_sort(order, order + njobs, [&](int x, int y) { return tile_cost(x) > tile_cost(y); });
   int64_t dig = 0, tiles = 0;
   int n = 0;
-  for (int j = 0; j < njobs; j++) {
+  for (int jj = 0; jj < njobs; jj++) {
+    const int j = order[jj];
     const Int8Args& g = jobs[j];
     const int D = digits[j];
     // whole products only: no resident planes, no split-K
