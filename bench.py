@@ -71,6 +71,30 @@ def traffic_for(workload, kernel, digest):
     return rec.get("hbm_bytes_per_launch")
 
 
+def binding_roof(plan, m, n, k, work, peak, unit, kern_ms):
+    """The roof that binds the dominant kernel, and its fraction.
+
+    Algorithmic HBM bytes: the binary64 operands read once and C written
+    once (FP64 words), or both operands' digit planes read once and C
+    written once (INT8 digits).  The roof that binds is the one whose time
+    at peak is the larger: the MFMA work (`work` at `peak` in `unit`) or
+    those bytes at 8 TB/s."""
+    mn, mk, kn = float(m) * n, float(m) * k, float(k) * n
+    if plan["form"] == 1:
+        alg_bytes = 8.0 * (mk + kn + mn)
+    else:
+        alg_bytes = plan["digits_a"] * mk + plan["digits_b"] * kn + 8.0 * mn
+    if alg_bytes / (HBM_PEAK_GBS * 1e9) > work / (peak * 1e12):
+        achieved = alg_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+        bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = work / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
+        bound = "mfma"
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "algorithmic_work_per_launch": work,
+            "algorithmic_bytes_per_launch": alg_bytes}
+
+
 def cpu_baseline(prob, A, B, budget_s=12.0):
     """The oracle, untuned, on the first rows of the same product."""
     import numpy as np
@@ -697,34 +721,9 @@ def main():
         form_desc = f"{plan['digits_a']} signed 8-bit digits per entry on INT8 MFMA"
     launches, total_ms = phases.get(phase, (0, 0.0))
     kern_ms = total_ms / max(launches, 1)
-    # Algorithmic HBM bytes of the dominant kernel: the binary64 operands
-    # read once and C written once (FP64 words), or both operands' digit
-    # planes read once and C written once (INT8 digits).  The roof that
-    # binds is the larger of the two times at peak: MFMA work or bytes.
-    mn, mk, kn = float(prob.m) * prob.n, float(prob.m) * prob.k, float(prob.k) * prob.n
-    if plan["form"] == 1:
-        alg_bytes = 8.0 * (mk + kn + mn)
-    else:
-        alg_bytes = plan["digits_a"] * mk + plan["digits_b"] * kn + 8.0 * mn
-    hbm_bound = alg_bytes / (HBM_PEAK_GBS * 1e9) > work / (peak * 1e12)
-    if hbm_bound:
-        achieved = alg_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
-        bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
-    else:
-        achieved = work / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
-        bound = "mfma"
-    roofline = {
-        "bound": bound,
-        "achieved": round(achieved, 3),
-        "peak": peak,
-        "unit": unit,
-        "frac": round(achieved / peak, 4),
-        "traffic": traffic_for(workload, kernel, digest),
-        "kernel": kernel,
-        "kernel_ms": round(kern_ms, 4),
-        "algorithmic_work_per_launch": work,
-        "algorithmic_bytes_per_launch": alg_bytes,
-    }
+    roofline = binding_roof(plan, prob.m, prob.n, prob.k, work, peak, unit, kern_ms)
+    roofline.update({"traffic": traffic_for(workload, kernel, digest), "kernel": kernel,
+                     "kernel_ms": round(kern_ms, 4)})
     shape = "square" if prob.m == prob.n == prob.k else "product"
     fill = ", all entries p - 1" if prob.fill == "pmax" else ""
     out = {
